@@ -1,0 +1,179 @@
+/*
+ * fsi.h - C ABI of the MI355X (gfx950) Faithful Shapley Interaction operator.
+ *
+ * The operator maps a value vector v over all 2^d coalitions of d players to
+ * the FSI scores E_S of every coalition S with |S| <= l (paper: "TT-FSI:
+ * Scalable Faithful Shapley Interactions via Tensor-Train"):
+ *
+ *   E_S = a(S) + sum_{T superset of S, |T| > l} w(|S|, |T|) a(T)
+ *
+ * with a the Moebius transform of v (Sec. 2.2, Eq. 3 and Eq. 4; Sec. 4.1,
+ * Eq. 5) and w the cardinality-only weight of Sec. 4.3, Eq. 7. The GPU
+ * computes it as a Moebius butterfly (Sec. 3.2) followed by the left-to-right
+ * MPO sweep over (|S|, |T|) counter states (Sec. 4.3 - 4.4, Algorithm 1),
+ * with the Moebius cores of the high sites precontracted into the final
+ * weight core (Sec. 4.5) in the fused algorithm.
+ *
+ * Conventions (all entry points):
+ *  - v is indexed by a d-bit mask: bit i set <=> player i in the coalition.
+ *    v(empty) need not be 0; then E_empty = v(empty).
+ *  - Outputs are in canonical order: ascending |S|, then ascending mask value
+ *    (slot 0 is the empty set). fsi_output_masks() returns that order.
+ *  - Device pointers are caller-owned HIP device memory, 16-byte aligned,
+ *    holding elements of the plan's storage dtype (FP64 or FP32). The library
+ *    never frees them. Outputs are always written in the storage dtype.
+ *  - Calls are asynchronous on the given HIP stream (NULL = default stream).
+ *    Bad arguments are rejected on the host before anything is launched and
+ *    leave the outputs untouched. HIP faults surface on the next call or on
+ *    the caller's synchronization.
+ *  - A plan owns its device tables and workspace; it is immutable after
+ *    creation. Concurrent applies of ONE plan on different streams race on
+ *    its workspace; use one plan per stream.
+ *  - No C++ exception crosses this ABI. Every non-OK status sets a
+ *    thread-local message readable with fsi_last_error().
+ */
+#ifndef FSI_MI355X_H
+#define FSI_MI355X_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FSI_OK = 0,
+  FSI_ERR_INVALID_ARG = 1,   /* a size, pointer, alignment or option is wrong */
+  FSI_ERR_UNSUPPORTED = 2,   /* no gfx950 device, or a combination not built */
+  FSI_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+  FSI_ERR_HIP = 4,           /* a HIP runtime call failed */
+  FSI_ERR_INTERNAL = 5
+} fsi_status;
+
+typedef enum { FSI_DTYPE_F64 = 0, FSI_DTYPE_F32 = 1 } fsi_dtype;
+
+/* Arithmetic of the path (the storage dtype is fsi_plan_opts.dtype).
+ * Correction weights (Eq. 7 and their precontracted forms) and the final
+ * cross-tile reduction are FP64 in every mode. */
+typedef enum {
+  FSI_PREC_F64 = 0,             /* FP64 storage, FP64 everywhere            */
+  FSI_PREC_F32 = 1,             /* FP32 Moebius, FP32 sweep accumulation    */
+  FSI_PREC_F32_COMPENSATED = 2, /* two-float Moebius, FP32 sweep            */
+  FSI_PREC_F32_FP64MOB = 3,     /* FP64 Moebius (cancellation-heavy input), */
+                                /* FP32 sweep                               */
+  FSI_PREC_F32_FP64REG = 4,     /* FP32 storage, FP64 Moebius and sweep     */
+  FSI_PREC_AUTO = 5             /* F64 for FP64 storage, F32_COMPENSATED    */
+                                /* for FP32 storage                         */
+} fsi_precision;
+
+typedef enum {
+  FSI_ALGO_AUTO = 0,
+  /* One read of v: per tile of the low b bits, the in-tile Moebius and the
+   * counter sweep; the high-site Moebius cores are precontracted into the
+   * final weights (Sec. 4.5 applied to the high sites); a small cross-tile
+   * reduction finishes. */
+  FSI_ALGO_FUSED = 1,
+  /* Literal Eq. 5 order: the full Moebius butterfly (low bits in LDS, high
+   * bits as strided passes) into the workspace, then the counter sweep with
+   * the weights of each tile's known high popcount, then the reduction. */
+  FSI_ALGO_TWO_PASS = 2
+} fsi_algo;
+
+typedef struct {
+  int32_t dtype;                 /* fsi_dtype, default FSI_DTYPE_F64         */
+  int32_t precision;             /* fsi_precision, default FSI_PREC_AUTO     */
+  int32_t algo;                  /* fsi_algo, default FSI_ALGO_AUTO          */
+  int32_t tile_bits;             /* b, 0 = choose (autotuned if enabled)     */
+  int32_t block_threads;         /* workgroup size, 0 = choose               */
+  int32_t autotune;              /* 1 = time candidate schedules at plan time*/
+  int32_t reserved[4];           /* must be 0                                */
+} fsi_plan_opts;
+
+typedef struct fsi_plan_s* fsi_plan_t;
+typedef struct fsi_batch_plan_s* fsi_batch_plan_t;
+
+/* Fill opts with the defaults listed above. */
+fsi_status fsi_default_opts(fsi_plan_opts* opts);
+
+/* M(d, l) = sum_{s=0..l} C(d, s): number of outputs (the empty set counts),
+ * or -1 if not 1 <= l <= d <= 30. */
+int64_t fsi_num_outputs(int d, int l);
+
+/* Plan for one instance size. Requires 1 <= d <= 30 and 1 <= l <= d
+ * (else FSI_ERR_INVALID_ARG; l = 0 is rejected). Uses the current HIP device,
+ * which must be gfx950 (else FSI_ERR_UNSUPPORTED). fsi_plan uses FP64
+ * storage and defaults. *out receives the plan (NULL on failure). */
+fsi_status fsi_plan(int d, int l, fsi_plan_t* out);
+fsi_status fsi_plan_ex(int d, int l, const fsi_plan_opts* opts, fsi_plan_t* out);
+
+/* Frees the plan's host tables, device tables and workspace. NULL is a
+ * no-op. Waits for the plan's in-flight work on the device first. */
+fsi_status fsi_plan_destroy(fsi_plan_t plan);
+
+/* Writes the M output masks of the plan, in canonical order, to host_masks
+ * (caller-owned, length fsi_num_outputs(d, l)). */
+fsi_status fsi_output_masks(fsi_plan_t plan, uint32_t* host_masks);
+
+/* Schedule actually chosen (tile bits b, workgroup size, algorithm,
+ * precision), for reporting. Any pointer may be NULL. */
+fsi_status fsi_plan_info(fsi_plan_t plan, int* tile_bits, int* block_threads,
+                         int* algo, int* precision);
+
+/* out_dev[k] = E_{S_k} for the plan's (d, l); v_dev has 2^d elements and is
+ * not modified; out_dev has M elements. Asynchronous on stream. */
+fsi_status fsi_apply(fsi_plan_t plan, const void* v_dev, void* out_dev,
+                     hipStream_t stream);
+
+/* Moebius transform alone (Sec. 3.2, Appendix B), in place on a_dev
+ * (2^d elements of the plan's storage dtype): for every bit i and every mask
+ * m with bit i set, a[m] -= a[m with bit i cleared]. Low bits are staged in
+ * LDS, high bits run as coalesced strided passes. */
+fsi_status fsi_mobius(fsi_plan_t plan, void* a_dev, hipStream_t stream);
+
+/* Batched plan over n instances of possibly different (d_i, l_i)
+ * (1 <= l_i <= d_i <= 30, n >= 1). Instance i reads values
+ * [value_offset[i], value_offset[i+1]) of one concatenated device array and
+ * writes outputs [out_offset[i], out_offset[i+1]) of another; both offset
+ * tables are prefix sums of 2^d_i and M(d_i, l_i) starting at 0. One apply
+ * is a fixed sequence of persistent kernel launches over a device work list,
+ * replayed from a captured HIP graph. */
+fsi_status fsi_plan_batched(int n, const int* d_host, const int* l_host,
+                            const fsi_plan_opts* opts, fsi_batch_plan_t* out);
+fsi_status fsi_batch_plan_destroy(fsi_batch_plan_t plan);
+
+/* Copies the offset tables (n + 1 int64 each) to host memory; either pointer
+ * may be NULL. */
+fsi_status fsi_batch_offsets(fsi_batch_plan_t plan, int64_t* value_offset,
+                             int64_t* out_offset);
+
+/* Applies the batched plan: values_dev holds value_offset[n] elements,
+ * out_dev out_offset[n] elements (storage dtype). Asynchronous on stream.
+ * The first call for a given (values_dev, out_dev) pair captures the
+ * launch sequence into a HIP graph; later calls with the same pointers
+ * replay it. */
+fsi_status fsi_apply_batched(fsi_batch_plan_t plan, const void* values_dev,
+                             void* out_dev, hipStream_t stream);
+
+/* Same as fsi_apply_batched but launches the kernels directly (no graph). */
+fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan,
+                                     const void* values_dev, void* out_dev,
+                                     hipStream_t stream);
+
+/* The kernel launches of one batched apply, for per-kernel timing: the
+ * fused algorithm has 2 stages (tile kernel: in-tile Moebius + counter sweep
+ * + final weights; then the cross-tile reduction), the two-pass algorithm
+ * has 3 + (number of strided high-bit Moebius passes). Running stages
+ * 0 .. n-1 in order on one stream equals fsi_apply_batched_nograph.
+ * fsi_batch_num_stages returns -1 for a NULL plan. */
+int fsi_batch_num_stages(fsi_batch_plan_t plan);
+fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev,
+                                   void* out_dev, int stage, hipStream_t stream);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* fsi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FSI_MI355X_H */

@@ -53,6 +53,9 @@ def _load():
         lib.oracle_fsi.restype = ctypes.c_int
         lib.oracle_mobius.argtypes = [dp, ctypes.c_int]
         lib.oracle_mobius.restype = None
+        lib.oracle_ranked_sums_int.argtypes = [ip, ctypes.c_int, ip, ctypes.c_int64,
+                                               ip, ip, ctypes.c_int]
+        lib.oracle_ranked_sums_int.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -84,3 +87,39 @@ def mobius_c(v) -> np.ndarray:
     d = a.size.bit_length() - 1
     lib.oracle_mobius(a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d)
     return a
+
+
+def fsi_exact_int(v, d: int, l: int, nthreads: int = 1) -> np.ndarray:
+    """FSI of an integer-valued v without rounding until the end: the Moebius
+    transform and the ranked superset sums A_t(S) are exact int64 (C twin),
+    E_S = a(S) + sum_{t > l} w(|S|, t) A_t(S) is summed in exact rationals
+    (weights of Eq. 7 as Fractions) and rounded once to FP64."""
+    if not (1 <= l <= d):
+        raise ValueError("need 1 <= l <= d")
+    vi = np.ascontiguousarray(np.asarray(v), dtype=np.int64)
+    if vi.size != 1 << d or not np.array_equal(vi, np.asarray(v)):
+        raise ValueError("v must hold 2^d integers")
+    if np.max(np.abs(vi)) * (1 << d) >= 2 ** 62:
+        raise ValueError("values too large for exact int64 accumulation")
+    lib = _load()
+    masks = np.ascontiguousarray(output_masks(d, l).astype(np.int64))
+    A = np.zeros((masks.size, d + 1), dtype=np.int64)
+    aS = np.zeros(masks.size, dtype=np.int64)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    rc = lib.oracle_ranked_sums_int(vi.ctypes.data_as(ip), d, masks.ctypes.data_as(ip),
+                                    masks.size, A.ctypes.data_as(ip), aS.ctypes.data_as(ip),
+                                    int(nthreads))
+    if rc != 0:
+        raise MemoryError("oracle_ranked_sums_int: allocation failed")
+    from fractions import Fraction
+    wq = {(s, t): weight_exact(s, t, l) for s in range(1, l + 1) for t in range(l + 1, d + 1)}
+    out = np.empty(masks.size, dtype=np.float64)
+    for k, S in enumerate(masks):
+        s = bin(int(S)).count("1")
+        val = Fraction(int(aS[k]))
+        if s >= 1:
+            for t in range(l + 1, d + 1):
+                if A[k, t]:
+                    val += wq[(s, t)] * int(A[k, t])
+        out[k] = float(val)
+    return out

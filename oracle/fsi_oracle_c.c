@@ -80,3 +80,48 @@ int oracle_fsi(const double *v, int d, int l, const double *W,
     free(a);
     return 0;
 }
+
+/*
+ * Exact variant for integer-valued v (e.g. the +/-1 vectors): the Moebius
+ * transform in int64 (exact while |v| * 2^d < 2^63) and, for every output S,
+ * the ranked superset sums A[k][t] = sum over supersets T of S with |T| = t
+ * of a(T), also in int64. The caller combines E_S = a(S) +
+ * sum_{t > l} w(|S|, t) A[k][t] in exact rational arithmetic.
+ * A has n_out rows of d + 1 entries; a_S receives a(S) per output.
+ */
+int oracle_ranked_sums_int(const int64_t *v, int d, const int64_t *masks,
+                           int64_t n_out, int64_t *A, int64_t *a_S, int nthreads)
+{
+    const int64_t n = (int64_t)1 << d;
+    const int64_t full = n - 1;
+    int64_t *a = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!a) return 1;
+    memcpy(a, v, sizeof(int64_t) * (size_t)n);
+    for (int i = 0; i < d; ++i) {
+        const int64_t bit = (int64_t)1 << i;
+        for (int64_t m = 0; m < n; ++m)
+            if (m & bit)
+                a[m] -= a[m ^ bit];
+    }
+#ifdef _OPENMP
+    if (nthreads < 1) nthreads = 1;
+    #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+#endif
+    for (int64_t k = 0; k < n_out; ++k) {
+        const int64_t S = masks[k];
+        int64_t *row = A + k * (d + 1);
+        for (int t = 0; t <= d; ++t) row[t] = 0;
+        const int64_t comp = full & ~S;
+        int64_t sub = 0;
+        for (;;) {
+            const int64_t T = S | sub;
+            row[__builtin_popcountll((unsigned long long)T)] += a[T];
+            if (sub == comp) break;
+            sub = (sub - comp) & comp;
+        }
+        a_S[k] = a[S];
+    }
+    free(a);
+    (void)nthreads;
+    return 0;
+}

@@ -1,0 +1,502 @@
+// C ABI of the FSI operator (declarations and contracts: include/fsi.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fsi.h"
+#include "fsi_internal.h"
+#include "fsi_kernels.h"
+
+using namespace fsi;
+
+namespace {
+
+thread_local std::string g_err;
+
+fsi_status fail(fsi_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(call)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      return fail(e_ == hipErrorOutOfMemory ? FSI_ERR_OUT_OF_MEMORY : FSI_ERR_HIP, \
+                  std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+bool device_is_gfx950(int* dev, int* n_cu, std::string* why) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    *why = "no HIP device";
+    return false;
+  }
+  if (hipGetDevice(dev) != hipSuccess) {
+    *why = "hipGetDevice failed";
+    return false;
+  }
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, *dev) != hipSuccess) {
+    *why = "hipGetDeviceProperties failed";
+    return false;
+  }
+  if (std::strncmp(p.gcnArchName, "gfx950", 6) != 0) {
+    *why = std::string("device is ") + p.gcnArchName + ", this library is built for gfx950";
+    return false;
+  }
+  *n_cu = p.multiProcessorCount;
+  return true;
+}
+
+}  // namespace
+
+struct fsi_batch_plan_s {
+  int n = 0, dtype = FSI_DTYPE_F64, prec = PREC_F64, algo = ALGO_FUSED;
+  int device = 0, n_cu = 256;
+  std::vector<int> d, l, cls_of;
+  std::vector<int64_t> voff, ooff;
+  std::vector<ClassHost> classes;
+  // device memory
+  void* arena = nullptr;           // tables, descriptors, work lists
+  double* Y = nullptr;
+  void* work = nullptr;            // two-pass Moebius workspace
+  LaunchArgs args{};
+  int tile_bits_reported = 0;
+  // graph cache
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* g_in = nullptr;
+  void* g_out = nullptr;
+};
+
+struct fsi_plan_s {
+  fsi_batch_plan_s* bp = nullptr;
+  int d = 0, l = 0;
+  std::vector<TileItem> dummy;
+};
+
+namespace {
+
+void free_batch(fsi_batch_plan_s* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  if (p->arena) (void)hipFree(p->arena);
+  if (p->Y) (void)hipFree(p->Y);
+  if (p->work) (void)hipFree(p->work);
+  delete p;
+}
+
+int resolve_prec(int dtype, int prec) {
+  if (prec == FSI_PREC_AUTO) return dtype == FSI_DTYPE_F64 ? PREC_F64 : PREC_F32_COMP;
+  return prec;
+}
+
+// Largest tile (b <= 12, b <= d) whose sweep state double-buffers in LDS.
+int choose_tile_bits(int d, int l, int prec, int requested) {
+  if (requested > 0) return requested;
+  for (int b = std::min(d, kMaxTileBits); b >= 1; --b) {
+    const int64_t need = std::max<int64_t>(2 * sweep_peak_entries(b, l) * (int64_t)sweep_elem_bytes(prec),
+                                           ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));
+    if (need <= kLdsBudget) return b;
+  }
+  return 1;
+}
+
+// Appends an aligned block to a host staging buffer and returns its offset.
+template <typename T>
+size_t stage(std::vector<unsigned char>& buf, const T* data, size_t count) {
+  size_t off = (buf.size() + 255) & ~(size_t)255;
+  buf.resize(off + count * sizeof(T));
+  if (count) std::memcpy(buf.data() + off, data, count * sizeof(T));
+  return off;
+}
+
+fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts* opts_in,
+                       bool single, fsi_batch_plan_s** out) {
+  *out = nullptr;
+  if (n < 1) return fail(FSI_ERR_INVALID_ARG, "n must be >= 1");
+  if (!dh || !lh) return fail(FSI_ERR_INVALID_ARG, "null d or l array");
+  fsi_plan_opts opts;
+  fsi_default_opts(&opts);
+  if (opts_in) opts = *opts_in;
+  for (int i = 0; i < 4; ++i)
+    if (opts.reserved[i] != 0) return fail(FSI_ERR_INVALID_ARG, "reserved option fields must be 0");
+  if (opts.dtype != FSI_DTYPE_F64 && opts.dtype != FSI_DTYPE_F32)
+    return fail(FSI_ERR_INVALID_ARG, "dtype must be FSI_DTYPE_F64 or FSI_DTYPE_F32");
+  if (opts.precision < 0 || opts.precision > FSI_PREC_AUTO)
+    return fail(FSI_ERR_INVALID_ARG, "unknown precision");
+  const int prec = resolve_prec(opts.dtype, opts.precision);
+  if (opts.dtype == FSI_DTYPE_F64 && prec != PREC_F64)
+    return fail(FSI_ERR_INVALID_ARG, "FP64 storage supports FSI_PREC_F64 only");
+  if (opts.dtype == FSI_DTYPE_F32 && prec == PREC_F64)
+    return fail(FSI_ERR_INVALID_ARG, "FP32 storage needs an FP32 precision mode");
+  if (opts.algo < 0 || opts.algo > FSI_ALGO_TWO_PASS)
+    return fail(FSI_ERR_INVALID_ARG, "unknown algo");
+  const int algo = opts.algo == FSI_ALGO_AUTO ? ALGO_FUSED : opts.algo;
+  if (opts.block_threads != 0 && opts.block_threads != kTileThreads)
+    return fail(FSI_ERR_UNSUPPORTED, "block_threads must be 0 or 512");
+  if (opts.tile_bits < 0 || opts.tile_bits > kMaxTileBits)
+    return fail(FSI_ERR_INVALID_ARG, "tile_bits must be in [0, 12]");
+  for (int i = 0; i < n; ++i) {
+    if (!(1 <= dh[i] && dh[i] <= kMaxD && 1 <= lh[i] && lh[i] <= dh[i]))
+      return fail(FSI_ERR_INVALID_ARG, "instance " + std::to_string(i) + ": need 1 <= l <= d <= 30");
+    if (opts.tile_bits > dh[i])
+      return fail(FSI_ERR_INVALID_ARG, "tile_bits larger than d");
+  }
+  int dev = 0, n_cu = 0;
+  std::string why;
+  if (!device_is_gfx950(&dev, &n_cu, &why)) return fail(FSI_ERR_UNSUPPORTED, why);
+
+  auto* P = new (std::nothrow) fsi_batch_plan_s();
+  if (!P) return fail(FSI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  P->n = n; P->dtype = opts.dtype; P->prec = prec; P->algo = algo;
+  P->device = dev; P->n_cu = n_cu;
+  P->d.assign(dh, dh + n);
+  P->l.assign(lh, lh + n);
+
+  // ---- classes ----
+  std::map<std::pair<int, int>, int> cls_index;
+  P->cls_of.resize(n);
+  for (int i = 0; i < n; ++i) {
+    auto key = std::make_pair(dh[i], lh[i]);
+    auto it = cls_index.find(key);
+    if (it == cls_index.end()) {
+      ClassHost C;
+      const int b = choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
+      std::string err = build_class(dh[i], lh[i], b, algo, &C);
+      if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
+      const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
+                                             ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));
+      if (need > kLdsBudget) {
+        free_batch(P);
+        return fail(FSI_ERR_INVALID_ARG, "tile_bits too large for LDS at this l and precision");
+      }
+      cls_index[key] = (int)P->classes.size();
+      P->classes.push_back(std::move(C));
+      it = cls_index.find(key);
+    }
+    P->cls_of[i] = it->second;
+  }
+  P->tile_bits_reported = P->classes[0].b;
+
+  // ---- instances, offsets, work lists ----
+  std::vector<InstDev> insts(n);
+  P->voff.assign(n + 1, 0);
+  P->ooff.assign(n + 1, 0);
+  int64_t ytot = 0, wtot = 0;
+  for (int i = 0; i < n; ++i) {
+    const ClassHost& C = P->classes[P->cls_of[i]];
+    P->voff[i + 1] = P->voff[i] + ((int64_t)1 << dh[i]);
+    P->ooff[i + 1] = P->ooff[i] + C.M;
+    insts[i].cls = P->cls_of[i];
+    insts[i].d = dh[i];
+    insts[i].voff = P->voff[i];
+    insts[i].ooff = P->ooff[i];
+    insts[i].yoff = ytot;
+    insts[i].woff = single ? 0 : wtot;
+    ytot += ((int64_t)1 << C.h) * C.Ysize;
+    wtot += (int64_t)1 << dh[i];
+  }
+  // tiles: larger tiles first, so a persistent grid finishes evenly
+  std::vector<TileItem> tiles;
+  for (int i = 0; i < n; ++i) {
+    const ClassHost& C = P->classes[P->cls_of[i]];
+    for (int64_t t = 0; t < ((int64_t)1 << C.h); ++t) tiles.push_back(TileItem{i, (int32_t)t});
+  }
+  std::stable_sort(tiles.begin(), tiles.end(), [&](const TileItem& a, const TileItem& b) {
+    return P->classes[P->cls_of[a.inst]].b > P->classes[P->cls_of[b.inst]].b;
+  });
+  // strided high-bit passes of the two-pass butterfly (also fsi_mobius)
+  std::vector<MobItem> mob[kMaxMobPasses];
+  int n_passes = 0;
+  for (int i = 0; i < n; ++i) {
+    const ClassHost& C = P->classes[P->cls_of[i]];
+    int lo = C.b, p = 0;
+    while (lo < dh[i]) {
+      const int G = std::min(6, dh[i] - lo);
+      const int cb = std::min(lo, kMaxTileBits - G);
+      if (p >= kMaxMobPasses) { free_batch(P); return fail(FSI_ERR_INTERNAL, "too many passes"); }
+      const int64_t nblk = (int64_t)1 << (dh[i] - G - cb);
+      for (int64_t bk = 0; bk < nblk; ++bk) mob[p].push_back(MobItem{i, lo, G, cb, bk});
+      lo += G;
+      ++p;
+    }
+    n_passes = std::max(n_passes, p);
+  }
+
+  // ---- device arena ----
+  std::vector<unsigned char> buf;
+  std::vector<ClassDev> cdev(P->classes.size());
+  struct Offs { size_t step_off, step_np, pat, ytab, lam, lam_soff, oinfo, osh; };
+  std::vector<Offs> co(P->classes.size());
+  for (size_t c = 0; c < P->classes.size(); ++c) {
+    const ClassHost& C = P->classes[c];
+    co[c].step_off = stage(buf, C.step_off.data(), C.step_off.size());
+    co[c].step_np = stage(buf, C.step_np.data(), C.step_np.size());
+    co[c].pat = stage(buf, C.pat.data(), C.pat.size());
+    co[c].ytab = stage(buf, C.ytab.data(), C.ytab.size());
+    co[c].lam = stage(buf, C.lam.data(), C.lam.size());
+    co[c].lam_soff = stage(buf, C.lam_soff.data(), C.lam_soff.size());
+    co[c].oinfo = stage(buf, C.oinfo.data(), C.oinfo.size());
+    co[c].osh = stage(buf, C.osh.data(), C.osh.size());
+  }
+  const size_t o_cls = stage(buf, cdev.data(), cdev.size());
+  const size_t o_inst = stage(buf, insts.data(), insts.size());
+  const size_t o_tiles = stage(buf, tiles.data(), tiles.size());
+  size_t o_mob[kMaxMobPasses] = {0, 0, 0, 0};
+  for (int p = 0; p < n_passes; ++p) o_mob[p] = stage(buf, mob[p].data(), mob[p].size());
+  const size_t o_ooff = stage(buf, P->ooff.data(), P->ooff.size());
+
+  hipError_t e = hipMalloc(&P->arena, buf.size());
+  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(tables) failed"); }
+  auto* A = static_cast<unsigned char*>(P->arena);
+  for (size_t c = 0; c < P->classes.size(); ++c) {
+    const ClassHost& C = P->classes[c];
+    ClassDev& D = cdev[c];
+    D.d = C.d; D.l = C.l; D.b = C.b; D.h = C.h; D.algo = C.algo;
+    D.M = C.M; D.Ysize = C.Ysize; D.lam_ublock = C.lam_ublock;
+    D.lds_elems = C.lds_elems; D.nfinal = C.nfinal;
+    D.step_off = reinterpret_cast<const int32_t*>(A + co[c].step_off);
+    D.step_np = reinterpret_cast<const int32_t*>(A + co[c].step_np);
+    D.pat = reinterpret_cast<const uint32_t*>(A + co[c].pat);
+    D.ytab = reinterpret_cast<const uint32_t*>(A + co[c].ytab);
+    D.lam = reinterpret_cast<const double*>(A + co[c].lam);
+    D.lam_soff = reinterpret_cast<const int32_t*>(A + co[c].lam_soff);
+    D.oinfo = reinterpret_cast<const uint32_t*>(A + co[c].oinfo);
+    D.osh = reinterpret_cast<const uint32_t*>(A + co[c].osh);
+  }
+  std::memcpy(buf.data() + o_cls, cdev.data(), cdev.size() * sizeof(ClassDev));
+  e = hipMemcpy(P->arena, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, "hipMemcpy(tables) failed"); }
+
+  e = hipMalloc(reinterpret_cast<void**>(&P->Y), std::max<int64_t>(ytot, 1) * sizeof(double));
+  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(Y) failed"); }
+  if (algo == ALGO_TWO_PASS) {
+    const size_t wbytes = (size_t)wtot *
+                          std::max(mob_elem_bytes(prec), (size_t)8);
+    e = hipMalloc(&P->work, wbytes);
+    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(work) failed"); }
+  }
+
+  // ---- schedule ----
+  size_t tile_lds = 0, mob_lds = 0;
+  for (const ClassHost& C : P->classes) {
+    tile_lds = std::max<size_t>(tile_lds, std::max<size_t>(2 * (size_t)C.lds_elems * sweep_elem_bytes(prec),
+                                                           ((size_t)1 << C.b) * mob_elem_bytes(prec)));
+    mob_lds = std::max<size_t>(mob_lds, ((size_t)1 << kMaxTileBits) * 8);
+  }
+  e = configure_kernels(prec, algo, tile_lds, mob_lds);
+  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, std::string("configure_kernels: ") + hipGetErrorString(e)); }
+  const int per_cu = std::max(1, std::min<int>(4, (int)((160 * 1024) / std::max<size_t>(tile_lds, 1))));
+  LaunchArgs& a = P->args;
+  a.prec = prec; a.algo = algo;
+  a.classes = reinterpret_cast<const ClassDev*>(A + o_cls);
+  a.insts = reinterpret_cast<const InstDev*>(A + o_inst);
+  a.n_inst = n;
+  a.tile_items = reinterpret_cast<const TileItem*>(A + o_tiles);
+  a.n_tile_items = (int)tiles.size();
+  a.n_mob_passes = n_passes;
+  for (int p = 0; p < kMaxMobPasses; ++p) {
+    a.mob_items[p] = p < n_passes ? reinterpret_cast<const MobItem*>(A + o_mob[p]) : nullptr;
+    a.n_mob_items[p] = p < n_passes ? (int)mob[p].size() : 0;
+  }
+  a.out_offset = reinterpret_cast<const int64_t*>(A + o_ooff);
+  a.total_out = P->ooff[n];
+  a.Y = P->Y;
+  a.work = P->work;
+  a.grid_tile = std::max(1, std::min<int>((int)tiles.size(), n_cu * per_cu));
+  a.grid_reduce = (int)std::max<int64_t>(1, std::min<int64_t>((a.total_out + 255) / 256, (int64_t)n_cu * 8));
+  a.tile_lds = tile_lds;
+  a.mob_lds = mob_lds;
+  *out = P;
+  return FSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fsi_status fsi_default_opts(fsi_plan_opts* opts) {
+  if (!opts) return fail(FSI_ERR_INVALID_ARG, "opts is NULL");
+  std::memset(opts, 0, sizeof(*opts));
+  opts->dtype = FSI_DTYPE_F64;
+  opts->precision = FSI_PREC_AUTO;
+  opts->algo = FSI_ALGO_AUTO;
+  return FSI_OK;
+}
+
+int64_t fsi_num_outputs(int d, int l) { return num_outputs(d, l); }
+
+fsi_status fsi_plan(int d, int l, fsi_plan_t* out) { return fsi_plan_ex(d, l, nullptr, out); }
+
+fsi_status fsi_plan_ex(int d, int l, const fsi_plan_opts* opts, fsi_plan_t* out) {
+  if (!out) return fail(FSI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!(1 <= d && d <= kMaxD && 1 <= l && l <= d))
+    return fail(FSI_ERR_INVALID_ARG, "need 1 <= l <= d <= 30");
+  fsi_batch_plan_s* bp = nullptr;
+  fsi_status st = build_batch(1, &d, &l, opts, true, &bp);
+  if (st != FSI_OK) return st;
+  auto* p = new (std::nothrow) fsi_plan_s();
+  if (!p) { free_batch(bp); return fail(FSI_ERR_OUT_OF_MEMORY, "host allocation failed"); }
+  p->bp = bp; p->d = d; p->l = l;
+  *out = p;
+  return FSI_OK;
+}
+
+fsi_status fsi_plan_destroy(fsi_plan_t plan) {
+  if (!plan) return FSI_OK;
+  free_batch(plan->bp);
+  delete plan;
+  return FSI_OK;
+}
+
+fsi_status fsi_output_masks(fsi_plan_t plan, uint32_t* host_masks) {
+  if (!plan || !host_masks) return fail(FSI_ERR_INVALID_ARG, "null plan or output");
+  const ClassHost& C = plan->bp->classes[0];
+  std::memcpy(host_masks, C.out_masks.data(), C.out_masks.size() * sizeof(uint32_t));
+  return FSI_OK;
+}
+
+fsi_status fsi_plan_info(fsi_plan_t plan, int* tile_bits, int* block_threads, int* algo,
+                         int* precision) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  if (tile_bits) *tile_bits = plan->bp->classes[0].b;
+  if (block_threads) *block_threads = kTileThreads;
+  if (algo) *algo = plan->bp->algo;
+  if (precision) *precision = plan->bp->prec;
+  return FSI_OK;
+}
+
+static fsi_status check_ptr(const void* p, const char* what) {
+  if (!p) return fail(FSI_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) & 15)
+    return fail(FSI_ERR_INVALID_ARG, std::string(what) + " is not 16-byte aligned");
+  return FSI_OK;
+}
+
+fsi_status fsi_apply(fsi_plan_t plan, const void* v_dev, void* out_dev, hipStream_t stream) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  fsi_status st;
+  if ((st = check_ptr(v_dev, "v_dev")) != FSI_OK) return st;
+  if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
+  LaunchArgs a = plan->bp->args;
+  a.values = v_dev;
+  a.out = out_dev;
+  HIP_TRY(launch_apply(a, stream));
+  return FSI_OK;
+}
+
+fsi_status fsi_mobius(fsi_plan_t plan, void* a_dev, hipStream_t stream) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  fsi_status st;
+  if ((st = check_ptr(a_dev, "a_dev")) != FSI_OK) return st;
+  LaunchArgs a = plan->bp->args;
+  a.work = a_dev;
+  a.prec = plan->bp->dtype == FSI_DTYPE_F64 ? PREC_F64 : PREC_F32;
+  HIP_TRY(launch_mobius(a, stream));
+  return FSI_OK;
+}
+
+fsi_status fsi_plan_batched(int n, const int* d_host, const int* l_host,
+                            const fsi_plan_opts* opts, fsi_batch_plan_t* out) {
+  if (!out) return fail(FSI_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  fsi_batch_plan_s* bp = nullptr;
+  fsi_status st = build_batch(n, d_host, l_host, opts, false, &bp);
+  if (st != FSI_OK) return st;
+  *out = bp;
+  return FSI_OK;
+}
+
+fsi_status fsi_batch_plan_destroy(fsi_batch_plan_t plan) {
+  free_batch(plan);
+  return FSI_OK;
+}
+
+fsi_status fsi_batch_offsets(fsi_batch_plan_t plan, int64_t* value_offset, int64_t* out_offset) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  if (value_offset) std::memcpy(value_offset, plan->voff.data(), (plan->n + 1) * sizeof(int64_t));
+  if (out_offset) std::memcpy(out_offset, plan->ooff.data(), (plan->n + 1) * sizeof(int64_t));
+  return FSI_OK;
+}
+
+fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan, const void* values_dev,
+                                     void* out_dev, hipStream_t stream) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  fsi_status st;
+  if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
+  if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
+  LaunchArgs a = plan->args;
+  a.values = values_dev;
+  a.out = out_dev;
+  HIP_TRY(launch_apply(a, stream));
+  return FSI_OK;
+}
+
+fsi_status fsi_apply_batched(fsi_batch_plan_t plan, const void* values_dev, void* out_dev,
+                             hipStream_t stream) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  fsi_status st;
+  if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
+  if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
+  if (!plan->exec || plan->g_in != values_dev || plan->g_out != out_dev) {
+    if (plan->exec) { HIP_TRY(hipGraphExecDestroy(plan->exec)); plan->exec = nullptr; }
+    if (plan->graph) { HIP_TRY(hipGraphDestroy(plan->graph)); plan->graph = nullptr; }
+    if (!plan->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+    LaunchArgs a = plan->args;
+    a.values = values_dev;
+    a.out = out_dev;
+    HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_apply(a, plan->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(plan->cap_stream, &g);
+    if (le != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(FSI_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(le));
+    }
+    if (ce != hipSuccess) return fail(FSI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    plan->graph = g;
+    HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+    plan->g_in = values_dev;
+    plan->g_out = out_dev;
+  }
+  HIP_TRY(hipGraphLaunch(plan->exec, stream));
+  return FSI_OK;
+}
+
+int fsi_batch_num_stages(fsi_batch_plan_t plan) {
+  if (!plan) { fail(FSI_ERR_INVALID_ARG, "null plan"); return -1; }
+  return num_stages(plan->args);
+}
+
+fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev, void* out_dev,
+                                   int stage, hipStream_t stream) {
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  fsi_status st;
+  if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
+  if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
+  if (stage < 0 || stage >= num_stages(plan->args))
+    return fail(FSI_ERR_INVALID_ARG, "stage out of range");
+  LaunchArgs a = plan->args;
+  a.values = values_dev;
+  a.out = out_dev;
+  HIP_TRY(launch_stage(a, stage, stream));
+  return FSI_OK;
+}
+
+const char* fsi_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Internal declarations shared by the host plan code and the HIP kernels.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace fsi {
+
+constexpr int kMaxD = 30;
+constexpr int kMaxTileBits = 12;   // LDS-staged tile: 2^b values
+constexpr int kLdsBudget = 150 * 1024;
+
+enum Algo : int32_t { ALGO_FUSED = 1, ALGO_TWO_PASS = 2 };
+enum Prec : int32_t {
+  PREC_F64 = 0, PREC_F32 = 1, PREC_F32_COMP = 2, PREC_F32_FP64MOB = 3,
+  PREC_F32_FP64REG = 4
+};
+
+// Per (d, l, b, algo) tables, as seen by the kernels (device pointers).
+struct ClassDev {
+  int32_t d, l, b, h, algo;
+  int32_t M;            // outputs per instance
+  int32_t Ysize;        // per-tile partial results (doubles)
+  int32_t lam_ublock;   // doubles per high-popcount block of the weight table
+  int32_t lds_elems;    // largest sweep state (entries) of one step
+  int32_t nfinal;       // final patterns (S_L, t_L)
+  const int32_t* step_off;  // [b+1] start of step k's entries in pat
+  const int32_t* step_np;   // [b+1] number of patterns after step k
+  const uint32_t* pat;      // (src0+1) | (src1+1) << 16 per output pattern
+  const uint32_t* ytab;     // [Ysize] final-pattern base | slot << 16 | s_L << 26
+  const double* lam;        // [(h+1) * lam_ublock]
+  const int32_t* lam_soff;  // [l+1] offset of the s_L block inside a u block
+  const uint32_t* oinfo;    // [M] Y offset of S_L | s_H << 24
+  const uint32_t* osh;      // [M] S_H (mask over the h high bits)
+};
+
+struct InstDev {
+  int32_t cls;       // index into the class array
+  int32_t d;
+  int64_t voff;      // first value
+  int64_t ooff;      // first output
+  int64_t yoff;      // first partial result (doubles) in the Y workspace
+  int64_t woff;      // first element of the Moebius workspace (two-pass)
+};
+
+// Host-side tables of one class (built once, uploaded into a device arena).
+struct ClassHost {
+  int d = 0, l = 0, b = 0, h = 0, algo = ALGO_FUSED;
+  int M = 0, Ysize = 0, lam_ublock = 0, lds_elems = 0, nfinal = 0;
+  std::vector<int32_t> step_off, step_np;
+  std::vector<uint32_t> pat, ytab, oinfo, osh, out_masks;
+  std::vector<double> lam;
+  std::vector<int32_t> lam_soff;
+};
+
+int64_t num_outputs(int d, int l);
+std::vector<uint32_t> canonical_masks(int d, int l);
+// Exact W(s, t) of the operator, rounded once to double (see fsi_tables.cpp).
+double weight_full(int s, int t, int l);
+// Largest sweep state of an in-tile sweep over b bits, in entries.
+int64_t sweep_peak_entries(int b, int l);
+// Builds all tables for one class; returns "" or an error message.
+std::string build_class(int d, int l, int b, int algo, ClassHost* out);
+
+}  // namespace fsi

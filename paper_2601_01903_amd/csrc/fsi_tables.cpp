@@ -1,0 +1,224 @@
+// Host-side plan tables for the FSI operator: exact weights, the counter
+// state tables of the in-tile MPO sweep, the per-tile weight tables of the
+// final core, and the output bookkeeping.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+
+#include "fsi_internal.h"
+
+namespace fsi {
+
+namespace {
+
+int64_t binom(int n, int k) {
+  if (k < 0 || n < 0 || k > n) return 0;
+  if (k > n - k) k = n - k;
+  __int128 r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;  // exact at each step
+  return (int64_t)r;
+}
+
+// W(s, t): the coefficient of a(T) in E_S for |S| = s, |T| = t, T superset
+// of S (closed form Eq. 3 + Eq. 4):
+//   1                 if t == s      (the Moebius term a(S))
+//   w(s, t) of Eq. 7  if t > l, s >= 1
+//   0                 otherwise.
+// w(s, t) = (-1)^(l-s) * s/(l+s) * C(l,s) * C(t-1,l) / C(t+l-1,l+s), whose
+// numerator and denominator are exact 64-bit integers for d, l <= 30; the
+// quotient is taken in binary128 (113-bit significand).
+__float128 weight_q(int s, int t, int l) {
+  if (t == s) return 1;
+  if (!(t > l && s >= 1)) return 0;
+  __int128 num = (__int128)s * binom(l, s) * binom(t - 1, l);
+  __int128 den = (__int128)(l + s) * binom(t + l - 1, l + s);
+  __float128 q = (__float128)num / (__float128)den;
+  return ((l - s) & 1) ? -q : q;
+}
+
+// Precontracted high-site weight (the Moebius cores of the h high sites
+// composed into the final weight core, Sec. 4.5): for a tile whose raw high
+// index U_H has popcount u, an output whose high part S_H gives
+// q = |S_H union U_H|, and a low superset of popcount t_L:
+//   lambda = sum_{m=0}^{h-q} C(h-q, m) (-1)^(q+m-u) W(s, t_L + q + m),
+// i.e. the sum over all high supersets T_H of S_H union U_H of
+// (-1)^(|T_H|-|U_H|) W(s, t_L + |T_H|).
+__float128 lambda_q(int s, int tL, int q, int u, int h, int l) {
+  __float128 acc = 0;
+  for (int m = 0; m <= h - q; ++m) {
+    __float128 term = (__float128)binom(h - q, m) * weight_q(s, tL + q + m, l);
+    acc += ((q + m - u) & 1) ? -term : term;
+  }
+  return acc;
+}
+
+int popc(uint64_t x) { return __builtin_popcountll(x); }
+
+}  // namespace
+
+double weight_full(int s, int t, int l) { return (double)weight_q(s, t, l); }
+
+int64_t num_outputs(int d, int l) {
+  if (!(1 <= l && l <= d && d <= kMaxD)) return -1;
+  int64_t m = 0;
+  for (int s = 0; s <= l; ++s) m += binom(d, s);
+  return m;
+}
+
+std::vector<uint32_t> canonical_masks(int d, int l) {
+  // ascending popcount, then ascending mask value
+  std::vector<uint32_t> out;
+  for (int s = 0; s <= std::min(l, d); ++s) {
+    if (s == 0) { out.push_back(0); continue; }
+    // Gosper's hack enumerates same-popcount masks in ascending order
+    uint64_t m = (1ull << s) - 1;
+    const uint64_t lim = 1ull << d;
+    while (m < lim) {
+      out.push_back((uint32_t)m);
+      uint64_t c = m & (~m + 1), r = m + c;
+      m = (((r ^ m) >> 2) / c) | r;
+    }
+  }
+  return out;
+}
+
+int64_t sweep_peak_entries(int b, int l) {
+  // after k sites: sum_{s <= min(k,l)} C(k,s) (k-s+1) patterns, each holding
+  // a suffix of 2^(b-k) inputs (Sec. 4.4, intermediate tensor with the
+  // output prefix compressed to |sigma| <= l).
+  int64_t peak = 0;
+  for (int k = 0; k <= b; ++k) {
+    int64_t p = 0;
+    for (int s = 0; s <= std::min(k, l); ++s) p += binom(k, s) * (k - s + 1);
+    peak = std::max(peak, p << (b - k));
+  }
+  return peak;
+}
+
+std::string build_class(int d, int l, int b, int algo, ClassHost* C) {
+  if (!(1 <= l && l <= d && d <= kMaxD)) return "invalid (d, l)";
+  if (!(1 <= b && b <= kMaxTileBits && b <= d)) return "invalid tile bits";
+  const int h = d - b;
+  C->d = d; C->l = l; C->b = b; C->h = h; C->algo = algo;
+  C->M = (int)num_outputs(d, l);
+
+  // ---- counter states of the in-tile sweep (Sec. 4.3 state space) ----
+  // Site k (k = 1..b) consumes tile bit b-k (most significant first). After
+  // site k a pattern is (sigma, t): sigma the output bits of the consumed
+  // sites read as a k-bit number (first site most significant), s =
+  // popcount(sigma) <= l, and t in [s, k] the running |T| counter.
+  // Patterns are stored sigma-major (ascending), t-minor; each holds the
+  // 2^(b-k) inputs of the unconsumed suffix.
+  std::vector<uint32_t> sig_prev{0};
+  std::vector<int32_t> base_prev{0};  // index of (sigma, t = s)
+  C->step_off.assign(b + 1, 0);
+  C->step_np.assign(b + 1, 0);
+  C->step_np[0] = 1;
+  C->pat.clear();
+  int64_t lds = 1ll << b;
+  for (int k = 1; k <= b; ++k) {
+    C->step_off[k] = (int32_t)C->pat.size();
+    std::vector<uint32_t> sig_next;
+    std::vector<int32_t> base_next;
+    int32_t np = 0;
+    for (size_t i = 0; i < sig_prev.size(); ++i) {
+      const uint32_t sg = sig_prev[i];
+      const int s = popc(sg);
+      const int32_t bp = base_prev[i];
+      auto idx_in = [&](int t) { return bp + (t - s); };  // t in [s, k-1]
+      for (int c = 0; c <= 1; ++c) {
+        const int s2 = s + c;
+        if (s2 > l) continue;
+        sig_next.push_back((sg << 1) | (uint32_t)c);
+        base_next.push_back(np);
+        for (int t2 = s2; t2 <= k; ++t2) {
+          int32_t src0 = -1, src1 = -1;  // (sigma, tau) = (c, 0) and (c, 1)
+          if (c == 0 && t2 <= k - 1) src0 = idx_in(t2);   // tau = 0: t kept
+          if (t2 - 1 >= s && t2 - 1 <= k - 1) src1 = idx_in(t2 - 1);  // tau = 1
+          if (src0 >= 0xFFFF || src1 >= 0xFFFF) return "sweep table too large";
+          C->pat.push_back((uint32_t)(src0 + 1) | ((uint32_t)(src1 + 1) << 16));
+          ++np;
+        }
+      }
+    }
+    C->step_np[k] = np;
+    lds = std::max<int64_t>(lds, (int64_t)np << (b - k));
+    sig_prev.swap(sig_next);
+    base_prev.swap(base_next);
+  }
+  C->lds_elems = (int)lds;
+  C->nfinal = C->step_np[b];
+  std::map<uint32_t, int32_t> final_base;  // S_L -> index of (S_L, t = s_L)
+  for (size_t i = 0; i < sig_prev.size(); ++i) final_base[sig_prev[i]] = base_prev[i];
+
+  // ---- slots of the per-tile partial results ----
+  // fused:    (s_H, j_H), s_H in [0, min(l - s_L, h)], j_H in [0, s_H],
+  //           slot = s_H (s_H + 1) / 2 + j_H   (j_H = |S_H & U_H|)
+  // two-pass: s_H in [0, min(l - s_L, h)], slot = s_H
+  auto nslot = [&](int sL) {
+    const int top = std::min(l - sL, h);
+    if (top < 0) return 0;
+    return algo == ALGO_FUSED ? (top + 1) * (top + 2) / 2 : top + 1;
+  };
+  const std::vector<uint32_t> low_masks = canonical_masks(b, std::min(l, b));
+  std::map<uint32_t, int32_t> yoff;
+  C->ytab.clear();
+  for (uint32_t SL : low_masks) {
+    const int sL = popc(SL);
+    yoff[SL] = (int32_t)C->ytab.size();
+    for (int sl = 0; sl < nslot(sL); ++sl) {
+      const int32_t fb = final_base.at(SL);
+      if (fb >= (1 << 16) || sl >= (1 << 10) || sL >= 64) return "Y table too large";
+      C->ytab.push_back((uint32_t)fb | ((uint32_t)sl << 16) | ((uint32_t)sL << 26));
+    }
+  }
+  C->Ysize = (int)C->ytab.size();
+  if (C->Ysize >= (1 << 24)) return "Y table too large";
+
+  // ---- final-core weights per high popcount u ----
+  C->lam_soff.assign(l + 1, 0);
+  int off = 0;
+  for (int sL = 0; sL <= l; ++sL) {
+    C->lam_soff[sL] = off;
+    if (sL <= b) off += nslot(sL) * (b + 1);
+  }
+  C->lam_ublock = off;
+  C->lam.assign((size_t)(h + 1) * off, 0.0);
+  for (int u = 0; u <= h; ++u) {
+    for (int sL = 0; sL <= std::min(l, b); ++sL) {
+      double* blk = &C->lam[(size_t)u * off + C->lam_soff[sL]];
+      const int top = std::min(l - sL, h);
+      for (int sH = 0; sH <= top; ++sH) {
+        const int s = sL + sH;
+        if (algo == ALGO_FUSED) {
+          for (int j = 0; j <= sH; ++j) {
+            const int slot = sH * (sH + 1) / 2 + j;
+            const bool ok = j <= u && (sH - j) <= (h - u);
+            const int q = u + sH - j;
+            for (int tL = sL; tL <= b; ++tL)
+              blk[slot * (b + 1) + tL] = ok ? (double)lambda_q(s, tL, q, u, h, l) : 0.0;
+          }
+        } else {
+          for (int tL = sL; tL <= b; ++tL)
+            blk[sH * (b + 1) + tL] = (double)weight_q(s, tL + u, l);
+        }
+      }
+    }
+  }
+
+  // ---- outputs ----
+  C->out_masks = canonical_masks(d, l);
+  C->oinfo.resize(C->out_masks.size());
+  C->osh.resize(C->out_masks.size());
+  const uint32_t lowmask = (b >= 32) ? 0xFFFFFFFFu : ((1u << b) - 1);
+  for (size_t k = 0; k < C->out_masks.size(); ++k) {
+    const uint32_t S = C->out_masks[k];
+    const uint32_t SL = S & lowmask, SH = S >> b;
+    C->oinfo[k] = (uint32_t)yoff.at(SL) | ((uint32_t)popc(SH) << 24);
+    C->osh[k] = SH;
+  }
+  return "";
+}
+
+}  // namespace fsi

@@ -373,3 +373,11 @@ def test_pins_catch_planted_oracle_mistakes(monkeypatch):
     monkeypatch.setattr(F, "superset_masks", subsets_instead)
     assert not _pins_pass(F.fsi)
     monkeypatch.setattr(F, "superset_masks", real_sup)
+
+
+@pytest.mark.parametrize("d,l", [(6, 6), (10, 2), (12, 4), (14, 3)])
+def test_exact_int_oracle_matches_pin(d, l):
+    v = np.random.default_rng(d + l).integers(-5, 6, size=1 << d)
+    ref = P.fsi_exact_int(v.astype(np.int64), d, l)
+    assert np.array_equal(oracle.fsi_exact_int(v, d, l), ref)
+    assert np.array_equal(oracle.fsi_exact_int(v, d, l, nthreads=4), ref)
