@@ -152,7 +152,12 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         b64_ms = ev0.elapsed_time(ev1) / args.steps
-        assert np.array_equal(ob64.cpu().numpy(), res64), "batched FP64 != per-instance FP64"
+        # The batched plan splits instances into a different number of work
+        # items than the single-instance plan, so the partial sums are added in
+        # another order: equal to rounding, not bit for bit.
+        rb = ob64.cpu().numpy()
+        bdiff = max(normwise(rb[i * M:(i + 1) * M], res64[i * M:(i + 1) * M]) for i in range(n))
+        assert bdiff < 1e-12, f"batched FP64 differs from per-instance FP64 by {bdiff:.3e}"
         bp64.close()
         del x64
         fp64 = {"plain_ms_per_pass": plain_ms, "plain_values_per_s": n * N / (plain_ms * 1e-3),

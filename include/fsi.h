@@ -87,8 +87,19 @@ typedef struct {
   int32_t tile_bits;             /* b, 0 = choose (autotuned if enabled)     */
   int32_t block_threads;         /* workgroup size, 0 = choose               */
   int32_t autotune;              /* 1 = time candidate schedules at plan time*/
-  int32_t reserved[4];           /* must be 0                                */
+  int32_t kernel;                /* fsi_kernel, default FSI_KERNEL_AUTO      */
+  int32_t reserved[3];           /* must be 0                                */
 } fsi_plan_opts;
+
+/* Tile kernel of the fused algorithm. The register-phase kernel covers
+ * FP32 storage (F32, F32_COMPENSATED, F32_FP64MOB) at d >= 12 and FP64 at
+ * d >= 11, with l <= 4 and d <= 24; the generic LDS kernel covers every
+ * (d, l). AUTO picks the register-phase kernel where it applies. */
+typedef enum {
+  FSI_KERNEL_AUTO = 0,
+  FSI_KERNEL_GENERIC = 1,
+  FSI_KERNEL_REGISTER = 2   /* FSI_ERR_UNSUPPORTED where it does not apply */
+} fsi_kernel;
 
 typedef struct fsi_plan_s* fsi_plan_t;
 typedef struct fsi_batch_plan_s* fsi_batch_plan_t;

@@ -68,6 +68,9 @@ struct fsi_batch_plan_s {
   void* arena = nullptr;           // tables, descriptors, work lists
   double* Y = nullptr;
   void* work = nullptr;            // two-pass Moebius workspace
+  double* partial = nullptr;       // register-phase kernel partial sums
+  std::vector<FastClassHost> fclasses;
+  std::vector<int> fast_of;        // per class: index into fclasses or -1
   LaunchArgs args{};
   int tile_bits_reported = 0;
   // graph cache
@@ -95,7 +98,22 @@ void free_batch(fsi_batch_plan_s* p) {
   if (p->arena) (void)hipFree(p->arena);
   if (p->Y) (void)hipFree(p->Y);
   if (p->work) (void)hipFree(p->work);
+  if (p->partial) (void)hipFree(p->partial);
   delete p;
+}
+
+// The register-phase kernel keeps its final-core entries in registers.
+bool fast_ysize_ok(int d, int l, int b) {
+  if (b > d) return false;
+  int64_t y = 0;
+  for (int sL = 0; sL <= l; ++sL) {
+    const int top = std::min(l - sL, d - b);
+    if (top < 0) continue;
+    int64_t c = 1;
+    for (int i = 0; i < sL; ++i) c = c * (b - i) / (i + 1);
+    y += c * (top + 1) * (top + 2) / 2;
+  }
+  return y < (int64_t)kFastKy * kFastThreads;
 }
 
 int resolve_prec(int dtype, int prec) {
@@ -131,8 +149,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   fsi_plan_opts opts;
   fsi_default_opts(&opts);
   if (opts_in) opts = *opts_in;
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 3; ++i)
     if (opts.reserved[i] != 0) return fail(FSI_ERR_INVALID_ARG, "reserved option fields must be 0");
+  if (opts.kernel < FSI_KERNEL_AUTO || opts.kernel > FSI_KERNEL_REGISTER)
+    return fail(FSI_ERR_INVALID_ARG, "unknown kernel");
   if (opts.dtype != FSI_DTYPE_F64 && opts.dtype != FSI_DTYPE_F32)
     return fail(FSI_ERR_INVALID_ARG, "dtype must be FSI_DTYPE_F64 or FSI_DTYPE_F32");
   if (opts.precision < 0 || opts.precision > FSI_PREC_AUTO)
@@ -174,15 +194,37 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     auto it = cls_index.find(key);
     if (it == cls_index.end()) {
       ClassHost C;
-      const int b = choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
+      // register-phase kernel: fused algorithm, l <= 4, tile of 12 bits
+      // (FP32 sweep) or 11 bits (FP64 sweep), at most 12 high bits
+      const int fb = fast_supported(prec) ? 8 + fast_pc(prec) : 0;
+      const bool want_fast = opts.kernel != FSI_KERNEL_GENERIC && algo == ALGO_FUSED && fb > 0 &&
+                             lh[i] <= 4 && dh[i] >= fb && dh[i] - fb <= 12 &&
+                             num_outputs(dh[i], lh[i]) <= (int64_t)kFastKmax * kFastThreads &&
+                             fast_ysize_ok(dh[i], lh[i], 8 + fast_pc(prec)) &&
+                             (opts.tile_bits == 0 || opts.tile_bits == fb);
+      if (opts.kernel == FSI_KERNEL_REGISTER && !want_fast) {
+        free_batch(P);
+        return fail(FSI_ERR_UNSUPPORTED, "register-phase kernel does not apply to instance " +
+                                             std::to_string(i));
+      }
+      const int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
       std::string err = build_class(dh[i], lh[i], b, algo, &C);
       if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
       const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
                                              ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));
-      if (need > kLdsBudget) {
+      if (!want_fast && need > kLdsBudget) {
         free_batch(P);
         return fail(FSI_ERR_INVALID_ARG, "tile_bits too large for LDS at this l and precision");
       }
+      int fidx = -1;
+      if (want_fast) {
+        FastClassHost F;
+        err = build_fast_class(C, 4, 4, fb - 8, kFastKy * kFastThreads, &F);
+        if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
+        fidx = (int)P->fclasses.size();
+        P->fclasses.push_back(std::move(F));
+      }
+      P->fast_of.push_back(fidx);
       cls_index[key] = (int)P->classes.size();
       P->classes.push_back(std::move(C));
       it = cls_index.find(key);
@@ -190,6 +232,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     P->cls_of[i] = it->second;
   }
   P->tile_bits_reported = P->classes[0].b;
+  if (n_cu <= 0) n_cu = 1;
 
   // ---- instances, offsets, work lists ----
   std::vector<InstDev> insts(n);
@@ -209,9 +252,54 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     ytot += ((int64_t)1 << C.h) * C.Ysize;
     wtot += (int64_t)1 << dh[i];
   }
-  // tiles: larger tiles first, so a persistent grid finishes evenly
+  // register-phase work items: runs of tiles of one instance, in the order of
+  // the class's tile list (high indices sorted by popcount, so the final
+  // weights change at most h + 1 times per instance)
+  std::vector<int32_t> torder;
+  std::vector<int32_t> tofs_of_fast(P->fclasses.size(), 0);
+  for (size_t f = 0; f < P->fclasses.size(); ++f) {
+    tofs_of_fast[f] = (int32_t)torder.size();
+    const int h = P->fclasses[f].h;
+    std::vector<int32_t> ord((size_t)1 << h);
+    for (size_t t = 0; t < ord.size(); ++t) ord[t] = (int32_t)t;
+    std::stable_sort(ord.begin(), ord.end(), [](int32_t x, int32_t y) {
+      return __builtin_popcount(x) < __builtin_popcount(y);
+    });
+    torder.insert(torder.end(), ord.begin(), ord.end());
+  }
+  int64_t fast_tiles = 0;
+  for (int i = 0; i < n; ++i)
+    if (P->fast_of[P->cls_of[i]] >= 0) fast_tiles += (int64_t)1 << P->classes[P->cls_of[i]].h;
+  int64_t chunk = 1;
+  while (chunk * 2 * n_cu * 2 <= fast_tiles) chunk *= 2;
+  std::vector<FastItem> fitems;
+  int64_t ptot = 0;
+  for (int i = 0; i < n; ++i) {
+    const int f = P->fast_of[P->cls_of[i]];
+    if (f < 0) continue;
+    const FastClassHost& F = P->fclasses[f];
+    const int64_t ntile = (int64_t)1 << F.h;
+    const int64_t cs = std::min<int64_t>(chunk, ntile);
+    insts[i].fast = 1;
+    insts[i].fcls = f;
+    insts[i].tofs = tofs_of_fast[f];
+    insts[i].pbase = ptot;
+    insts[i].nitems = (int32_t)((ntile + cs - 1) / cs);
+    for (int64_t tb = 0; tb < ntile; tb += cs) {
+      fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min(ntile, tb + cs), 0, ptot});
+      ptot += F.M;
+    }
+  }
+  // every tile of every instance (standalone Moebius low pass)
+  std::vector<TileItem> all_tiles;
+  for (int i = 0; i < n; ++i) {
+    const ClassHost& C = P->classes[P->cls_of[i]];
+    for (int64_t t = 0; t < ((int64_t)1 << C.h); ++t) all_tiles.push_back(TileItem{i, (int32_t)t});
+  }
+  // generic tiles: larger tiles first, so a persistent grid finishes evenly
   std::vector<TileItem> tiles;
   for (int i = 0; i < n; ++i) {
+    if (insts[i].fast) continue;
     const ClassHost& C = P->classes[P->cls_of[i]];
     for (int64_t t = 0; t < ((int64_t)1 << C.h); ++t) tiles.push_back(TileItem{i, (int32_t)t});
   }
@@ -252,9 +340,28 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].oinfo = stage(buf, C.oinfo.data(), C.oinfo.size());
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
+  std::vector<FastClassDev> fdev(P->fclasses.size());
+  struct FOffs { size_t u3tab, unit_s, row2, zbase, ytab, lam, lam_soff, gsize, ometa; };
+  std::vector<FOffs> fo(P->fclasses.size());
+  for (size_t f = 0; f < P->fclasses.size(); ++f) {
+    const FastClassHost& F = P->fclasses[f];
+    fo[f].u3tab = stage(buf, F.u3tab.data(), F.u3tab.size());
+    fo[f].unit_s = stage(buf, F.unit_s.data(), F.unit_s.size());
+    fo[f].row2 = stage(buf, F.row2.data(), F.row2.size());
+    fo[f].zbase = stage(buf, F.zbase.data(), F.zbase.size());
+    fo[f].ytab = stage(buf, F.ytab.data(), F.ytab.size());
+    fo[f].lam = stage(buf, F.lam.data(), F.lam.size());
+    fo[f].lam_soff = stage(buf, F.lam_soff.data(), F.lam_soff.size());
+    fo[f].gsize = stage(buf, F.gsize.data(), F.gsize.size());
+    fo[f].ometa = stage(buf, F.ometa.data(), F.ometa.size());
+  }
+  const size_t o_fcls = stage(buf, fdev.data(), fdev.size());
+  const size_t o_fitems = stage(buf, fitems.data(), fitems.size());
+  const size_t o_torder = stage(buf, torder.data(), torder.size());
   const size_t o_cls = stage(buf, cdev.data(), cdev.size());
   const size_t o_inst = stage(buf, insts.data(), insts.size());
   const size_t o_tiles = stage(buf, tiles.data(), tiles.size());
+  const size_t o_all_tiles = stage(buf, all_tiles.data(), all_tiles.size());
   size_t o_mob[kMaxMobPasses] = {0, 0, 0, 0};
   for (int p = 0; p < n_passes; ++p) o_mob[p] = stage(buf, mob[p].data(), mob[p].size());
   const size_t o_ooff = stage(buf, P->ooff.data(), P->ooff.size());
@@ -278,6 +385,40 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.osh = reinterpret_cast<const uint32_t*>(A + co[c].osh);
   }
   std::memcpy(buf.data() + o_cls, cdev.data(), cdev.size() * sizeof(ClassDev));
+  size_t fast_lds = 0;
+  for (size_t f = 0; f < P->fclasses.size(); ++f) {
+    const FastClassHost& F = P->fclasses[f];
+    FastClassDev& D = fdev[f];
+    D.d = F.d; D.l = F.l; D.b = F.b; D.h = F.h; D.M = F.M; D.n3 = F.n3; D.nzi = F.nzi;
+    D.Ysize = F.Ysize; D.lam_ublock = F.lam_ublock;
+    const size_t NC = (size_t)1 << F.PC;
+    // region B data: raw-tile transposes | S2 (+ one spare row per thread) | Y
+    size_t data = std::max<size_t>(((size_t)F.P2 + 1) * NC * sweep_elem_bytes(prec) +
+                                       (size_t)kFastThreads * sweep_elem_bytes(prec),
+                                   (size_t)F.Ysize * 8);
+    data = std::max<size_t>(data, ((size_t)1 << F.b) * (prec == PREC_F32 ? 4 : 8));
+    D.tabo = (int32_t)((data + 255) & ~(size_t)255);
+    const size_t tab_ints = 256 + 16 + NC + 8 + 8;
+    D.lamo = (int32_t)((tab_ints * 4 + 15) & ~(size_t)15);
+    const size_t need = fast_regA_bytes(prec, F.nzi) + D.tabo + D.lamo + (size_t)F.lam_ublock * 8;
+    if (need > 160 * 1024) {
+      free_batch(P);
+      return fail(FSI_ERR_INTERNAL, "register-phase kernel does not fit in LDS");
+    }
+    fast_lds = std::max(fast_lds, need);
+    D.u3tab = reinterpret_cast<const int32_t*>(A + fo[f].u3tab);
+    D.unit_s = reinterpret_cast<const int32_t*>(A + fo[f].unit_s);
+    D.row2 = reinterpret_cast<const int32_t*>(A + fo[f].row2);
+    D.zbase = reinterpret_cast<const int32_t*>(A + fo[f].zbase);
+    D.ytab = reinterpret_cast<const uint32_t*>(A + fo[f].ytab);
+    D.lam = reinterpret_cast<const double*>(A + fo[f].lam);
+    D.lam_soff = reinterpret_cast<const int32_t*>(A + fo[f].lam_soff);
+    D.gsize = reinterpret_cast<const int32_t*>(A + fo[f].gsize);
+    D.ometa = reinterpret_cast<const uint32_t*>(A + fo[f].ometa);
+  }
+  std::memcpy(buf.data() + o_fcls, fdev.data(), fdev.size() * sizeof(FastClassDev));
+  // instance descriptors carry the fast fields filled above
+  std::memcpy(buf.data() + o_inst, insts.data(), insts.size() * sizeof(InstDev));
   e = hipMemcpy(P->arena, buf.data(), buf.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, "hipMemcpy(tables) failed"); }
 
@@ -290,15 +431,24 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(work) failed"); }
   }
 
+  if (ptot > 0) {
+    e = hipMalloc(reinterpret_cast<void**>(&P->partial), ptot * sizeof(double));
+    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(partial) failed"); }
+  }
+
   // ---- schedule ----
-  size_t tile_lds = 0, mob_lds = 0;
-  for (const ClassHost& C : P->classes) {
+  // Moebius passes stage at most 2^12 elements of at most 8 bytes
+  const size_t mob_lds = ((size_t)1 << kMaxTileBits) * 8;
+  size_t tile_lds = 0;
+  for (size_t c = 0; c < P->classes.size(); ++c) {
+    const ClassHost& C = P->classes[c];
+    if (P->fast_of[c] >= 0) continue;
     tile_lds = std::max<size_t>(tile_lds, std::max<size_t>(2 * (size_t)C.lds_elems * sweep_elem_bytes(prec),
                                                            ((size_t)1 << C.b) * mob_elem_bytes(prec)));
-    mob_lds = std::max<size_t>(mob_lds, ((size_t)1 << kMaxTileBits) * 8);
   }
   e = configure_kernels(prec, algo, tile_lds, mob_lds);
   if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, std::string("configure_kernels: ") + hipGetErrorString(e)); }
+  if (tile_lds == 0) tile_lds = 1024;
   const int per_cu = std::max(1, std::min<int>(4, (int)((160 * 1024) / std::max<size_t>(tile_lds, 1))));
   LaunchArgs& a = P->args;
   a.prec = prec; a.algo = algo;
@@ -307,6 +457,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.n_inst = n;
   a.tile_items = reinterpret_cast<const TileItem*>(A + o_tiles);
   a.n_tile_items = (int)tiles.size();
+  a.all_tiles = reinterpret_cast<const TileItem*>(A + o_all_tiles);
+  a.n_all_tiles = (int)all_tiles.size();
   a.n_mob_passes = n_passes;
   for (int p = 0; p < kMaxMobPasses; ++p) {
     a.mob_items[p] = p < n_passes ? reinterpret_cast<const MobItem*>(A + o_mob[p]) : nullptr;
@@ -316,10 +468,26 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.total_out = P->ooff[n];
   a.Y = P->Y;
   a.work = P->work;
-  a.grid_tile = std::max(1, std::min<int>((int)tiles.size(), n_cu * per_cu));
+  a.grid_tile = std::max(1, std::min<int>((int)std::max(tiles.size(), all_tiles.size()), n_cu * per_cu));
   a.grid_reduce = (int)std::max<int64_t>(1, std::min<int64_t>((a.total_out + 255) / 256, (int64_t)n_cu * 8));
   a.tile_lds = tile_lds;
   a.mob_lds = mob_lds;
+  a.partial = P->partial;
+  a.fast = FastLaunch{};
+  a.fast.n_items = (int)fitems.size();
+  if (!fitems.empty()) {
+    e = configure_fast(prec, fast_lds);
+    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, std::string("configure_fast: ") + hipGetErrorString(e)); }
+    a.fast.prec = prec;
+    a.fast.classes = reinterpret_cast<const FastClassDev*>(A + o_fcls);
+    a.fast.insts = a.insts;
+    a.fast.items = reinterpret_cast<const FastItem*>(A + o_fitems);
+    a.fast.torder = reinterpret_cast<const int32_t*>(A + o_torder);
+    a.fast.partial = P->partial;
+    a.fast.lds = fast_lds;
+    const int per_cu = std::max(1, (int)((160 * 1024) / fast_lds));
+    a.fast.grid = std::max(1, std::min<int>((int)fitems.size(), n_cu * per_cu));
+  }
   *out = P;
   return FSI_OK;
 }

@@ -19,13 +19,46 @@ struct MobItem {
   int64_t block;            // (bits above the group) * 2^(lo-cb) + low chunk
 };
 
+// Register-phase kernel (fsi_fast.hip)
+constexpr int kFastThreads = 256;
+constexpr int kFastKmax = 25;      // outputs per thread: M <= 25 * 256
+constexpr int kFastKy = 6;         // final-core entries per thread: Ysize <= 6 * 256 (padded)
+
+struct FastItem {
+  int32_t inst, tb, te, pad;       // tiles [tb, te) of the instance's tile order
+  int64_t pofs;                    // partial sums of this item
+};
+
+struct FastLaunch {
+  int prec;
+  const FastClassDev* classes;
+  const InstDev* insts;
+  const FastItem* items;
+  int n_items;
+  const void* vals32;
+  const void* vals64;
+  const int32_t* torder;
+  double* partial;
+  int grid;
+  size_t lds;
+};
+
+hipError_t configure_fast(int prec, size_t lds);
+hipError_t launch_fast(const FastLaunch& f, hipStream_t st);
+int fast_pc(int prec);
+bool fast_supported(int prec);
+// LDS bytes of region A (phase-1 / final states) for a precision.
+size_t fast_regA_bytes(int prec, int nzi);
+
 struct LaunchArgs {
   int prec, algo;
   const ClassDev* classes;
   const InstDev* insts;
   int n_inst;
-  const TileItem* tile_items;
+  const TileItem* tile_items;     // tiles of the generic tile kernel
   int n_tile_items;
+  const TileItem* all_tiles;      // every tile (standalone Moebius)
+  int n_all_tiles;
   const MobItem* mob_items[kMaxMobPasses];
   int n_mob_items[kMaxMobPasses];
   int n_mob_passes;
@@ -37,6 +70,8 @@ struct LaunchArgs {
   double* Y;
   int grid_tile, grid_reduce;
   size_t tile_lds, mob_lds;
+  const double* partial;      // register-phase kernel partial sums
+  FastLaunch fast;            // n_items == 0: no register-phase stage
 };
 
 // Sets the dynamic-LDS limits of the kernels a plan will launch (call once

@@ -179,7 +179,8 @@ template <typename OutT>
 __global__ void __launch_bounds__(256)
 reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               int n_inst, const int64_t* __restrict__ out_offset, int64_t total,
-              const double* __restrict__ Y, OutT* __restrict__ out) {
+              const double* __restrict__ Y, const double* __restrict__ partial,
+              OutT* __restrict__ out) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = n_inst;
@@ -188,8 +189,16 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
       if (out_offset[mid] <= g) lo = mid; else hi = mid;
     }
     const InstDev I = insts[lo];
-    const ClassDev* C = classes + I.cls;
     const int k = (int)(g - out_offset[lo]);
+    if (I.fast) {
+      const int64_t M = out_offset[lo + 1] - out_offset[lo];
+      const double* P = partial + I.pbase + k;
+      double acc = 0.0;
+      for (int j = 0; j < I.nitems; ++j) acc += P[(int64_t)j * M];
+      out[I.ooff + k] = (OutT)acc;
+      continue;
+    }
+    const ClassDev* C = classes + I.cls;
     const uint32_t oi = C->oinfo[k];
     const uint32_t SH = C->osh[k];
     const int yo = (int)(oi & 0xFFFFFFu);
@@ -334,8 +343,10 @@ hipError_t configure_kernels(int prec, int algo, size_t tile_lds, size_t mob_lds
 }
 
 int num_stages(const LaunchArgs& a) {
-  // fused: tile, reduce; two-pass: Moebius low pass, high passes, tile, reduce
-  return a.algo == ALGO_FUSED ? 2 : 3 + a.n_mob_passes;
+  // fused: [register-phase kernel], [generic tile kernel], reduce
+  // two-pass: Moebius low pass, high passes, tile, reduce
+  if (a.algo == ALGO_FUSED) return (a.fast.n_items > 0) + (a.n_tile_items > 0) + 1;
+  return 3 + a.n_mob_passes;
 }
 
 template <typename InT, typename MobT, typename SwT>
@@ -344,9 +355,15 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   if (stage < 0 || stage > last) return hipErrorInvalidValue;
   if (stage == last) {
     hipLaunchKernelGGL(reduce_kernel<InT>, dim3(a.grid_reduce), dim3(256), 0, st, a.classes,
-                       a.insts, a.n_inst, a.out_offset, a.total_out, a.Y,
+                       a.insts, a.n_inst, a.out_offset, a.total_out, a.Y, a.partial,
                        static_cast<InT*>(a.out));
     return hipGetLastError();
+  }
+  if (a.algo == ALGO_FUSED && a.fast.n_items > 0 && stage == 0) {
+    FastLaunch f = a.fast;
+    f.vals32 = a.values;
+    f.vals64 = a.values;
+    return launch_fast(f, st);
   }
   if (a.algo == ALGO_FUSED) {
     hipLaunchKernelGGL((tile_kernel<InT, MobT, SwT, true>), dim3(a.grid_tile), dim3(kTileThreads),
@@ -400,7 +417,7 @@ hipError_t launch_mobius_t(const LaunchArgs& a, hipStream_t st) {
   // in place on the caller's buffer: the instance's work offset is 0 and
   // the source is the buffer itself (src_is_values = 0 -> offset woff)
   hipLaunchKernelGGL(km, dim3(a.grid_tile), dim3(kTileThreads), a.mob_lds, st, a.classes,
-                     a.insts, a.tile_items, a.n_tile_items, static_cast<const T*>(a.work),
+                     a.insts, a.all_tiles, a.n_all_tiles, static_cast<const T*>(a.work),
                      static_cast<T*>(a.work), 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   auto kh = mobius_high_kernel<T>;

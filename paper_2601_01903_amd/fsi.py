@@ -22,6 +22,7 @@ DTYPES = {"f64": 0, "f32": 1}
 PRECISIONS = {"f64": 0, "f32": 1, "f32_compensated": 2, "f32_fp64mob": 3,
               "f32_fp64reg": 4, "auto": 5}
 ALGOS = {"auto": 0, "fused": 1, "two_pass": 2}
+KERNELS = {"auto": 0, "generic": 1, "register": 2}
 
 # names of every function include/fsi.h declares
 EXPORTS = ["fsi_default_opts", "fsi_num_outputs", "fsi_plan", "fsi_plan_ex",
@@ -41,7 +42,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("algo", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 _lib = None
@@ -97,7 +98,7 @@ def num_outputs(d: int, l: int) -> int:
 
 
 def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
-              block_threads=0) -> Opts:
+              block_threads=0, kernel="auto") -> Opts:
     o = Opts()
     _check(load().fsi_default_opts(ctypes.byref(o)), "fsi_default_opts")
     o.dtype = DTYPES[dtype]
@@ -105,6 +106,7 @@ def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
     o.algo = ALGOS[algo]
     o.tile_bits = int(tile_bits)
     o.block_threads = int(block_threads)
+    o.kernel = KERNELS[kernel]
     return o
 
 
@@ -130,11 +132,12 @@ class Plan:
     """fsi_plan_ex / fsi_apply for one (d, l)."""
 
     def __init__(self, d: int, l: int, dtype: str = "f64", precision: str = "auto",
-                 algo: str = "auto", tile_bits: int = 0, block_threads: int = 0):
+                 algo: str = "auto", tile_bits: int = 0, block_threads: int = 0,
+                 kernel: str = "auto"):
         lib = load()
         self.d, self.l, self.dtype = d, l, dtype
         self._h = ctypes.c_void_p()
-        opts = make_opts(dtype, precision, algo, tile_bits, block_threads)
+        opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel)
         _check(lib.fsi_plan_ex(d, l, ctypes.byref(opts), ctypes.byref(self._h)), "fsi_plan_ex")
         self.M = num_outputs(d, l)
 
@@ -187,7 +190,7 @@ class BatchPlan:
 
     def __init__(self, ds: Sequence[int], ls: Sequence[int], dtype: str = "f32",
                  precision: str = "auto", algo: str = "auto", tile_bits: int = 0,
-                 block_threads: int = 0):
+                 block_threads: int = 0, kernel: str = "auto"):
         lib = load()
         n = len(ds)
         if len(ls) != n:
@@ -196,7 +199,7 @@ class BatchPlan:
         self.ds, self.ls = list(ds), list(ls)
         darr = (ctypes.c_int * n)(*ds)
         larr = (ctypes.c_int * n)(*ls)
-        opts = make_opts(dtype, precision, algo, tile_bits, block_threads)
+        opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel)
         self._h = ctypes.c_void_p()
         _check(lib.fsi_plan_batched(n, darr, larr, ctypes.byref(opts), ctypes.byref(self._h)),
                "fsi_plan_batched")

@@ -106,6 +106,35 @@ def test_d20_fp32_modes(prec, algo):
     assert np.all(np.isfinite(gotp))
 
 
+@pytest.mark.parametrize("kernel", ["generic", "register"])
+@pytest.mark.parametrize("prec", ["f32", "f32_compensated", "f32_fp64mob"])
+@pytest.mark.parametrize("d,l", [(12, 4), (13, 2), (16, 3), (20, 4), (20, 1)])
+def test_register_kernel_fp32(d, l, prec, kernel):
+    say(f"[case] register-phase check d={d} l={l} {prec} kernel={kernel}")
+    if d == 20:
+        g, v = games.d20_tree(0)
+        if l == 1:
+            v = games.d20_batch_instance(1)[1]
+    else:
+        g = games.tree_game(d, 60, 5, games.rng_for(95, d * 10 + l))
+        v = games.tree_values(g)
+    v32 = v.astype(np.float32)
+    ref = oracle.fsi_c(v32.astype(np.float64), d, l, nthreads=8)
+    got, info = gpu_apply(v32, d, l, dtype="f32", precision=prec, kernel=kernel)
+    err = normwise(got, ref)
+    say(f"  tile_bits={info['tile_bits']} err={err:.3e}")
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("kernel", ["generic", "register"])
+@pytest.mark.parametrize("d,l", [(11, 4), (12, 3), (17, 2), (20, 4)])
+def test_register_kernel_fp64_exact(d, l, kernel):
+    say(f"[case] register-phase FP64 d={d} l={l} kernel={kernel}")
+    v = np.random.default_rng(3000 + d * 7 + l).integers(-4, 5, size=1 << d).astype(np.float64)
+    got, _ = gpu_apply(v, d, l, kernel=kernel)
+    assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=8)) < 1e-12
+
+
 @pytest.mark.parametrize("d,l,tb", [(1, 1, 0), (2, 2, 0), (5, 5, 0), (9, 9, 0), (12, 4, 0),
                                     (13, 4, 0), (10, 3, 3), (11, 1, 4), (16, 2, 0),
                                     (15, 4, 7), (17, 3, 0)])
