@@ -102,20 +102,6 @@ void free_batch(fsi_batch_plan_s* p) {
   delete p;
 }
 
-// The register-phase kernel keeps its final-core entries in registers.
-bool fast_ysize_ok(int d, int l, int b) {
-  if (b > d) return false;
-  int64_t y = 0;
-  for (int sL = 0; sL <= l; ++sL) {
-    const int top = std::min(l - sL, d - b);
-    if (top < 0) continue;
-    int64_t c = 1;
-    for (int i = 0; i < sL; ++i) c = c * (b - i) / (i + 1);
-    y += c * (top + 1) * (top + 2) / 2;
-  }
-  return y < (int64_t)kFastKy * kFastThreads;
-}
-
 int resolve_prec(int dtype, int prec) {
   if (prec == FSI_PREC_AUTO) return dtype == FSI_DTYPE_F64 ? PREC_F64 : PREC_F32_COMP;
   return prec;
@@ -194,13 +180,13 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     auto it = cls_index.find(key);
     if (it == cls_index.end()) {
       ClassHost C;
-      // register-phase kernel: fused algorithm, l <= 4, tile of 12 bits
-      // (FP32 sweep) or 11 bits (FP64 sweep), at most 12 high bits
-      const int fb = fast_supported(prec) ? 8 + fast_pc(prec) : 0;
-      const bool want_fast = opts.kernel != FSI_KERNEL_GENERIC && algo == ALGO_FUSED && fb > 0 &&
-                             lh[i] <= 4 && dh[i] >= fb && dh[i] - fb <= 12 &&
+      // register-phase kernel: fused algorithm, l <= 4, tile of 11 bits,
+      // at most 12 high bits, at most 25 outputs per thread
+      const int fb = kFastTileBits;
+      const bool want_fast = opts.kernel != FSI_KERNEL_GENERIC && algo == ALGO_FUSED &&
+                             fast_supported(prec) && lh[i] <= kFastMaxL && dh[i] >= fb &&
+                             dh[i] - fb <= 12 &&
                              num_outputs(dh[i], lh[i]) <= (int64_t)kFastKmax * kFastThreads &&
-                             fast_ysize_ok(dh[i], lh[i], 8 + fast_pc(prec)) &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
       if (opts.kernel == FSI_KERNEL_REGISTER && !want_fast) {
         free_batch(P);
@@ -219,7 +205,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       int fidx = -1;
       if (want_fast) {
         FastClassHost F;
-        err = build_fast_class(C, 4, 4, fb - 8, kFastKy * kFastThreads, &F);
+        err = build_fast_class(C, &F);
         if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
         fidx = (int)P->fclasses.size();
         P->fclasses.push_back(std::move(F));
@@ -341,19 +327,14 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
   std::vector<FastClassDev> fdev(P->fclasses.size());
-  struct FOffs { size_t u3tab, unit_s, row2, zbase, ytab, lam, lam_soff, gsize, ometa; };
+  struct FOffs { size_t lam, ometa, unit_mask, zrow; };
   std::vector<FOffs> fo(P->fclasses.size());
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
-    fo[f].u3tab = stage(buf, F.u3tab.data(), F.u3tab.size());
-    fo[f].unit_s = stage(buf, F.unit_s.data(), F.unit_s.size());
-    fo[f].row2 = stage(buf, F.row2.data(), F.row2.size());
-    fo[f].zbase = stage(buf, F.zbase.data(), F.zbase.size());
-    fo[f].ytab = stage(buf, F.ytab.data(), F.ytab.size());
     fo[f].lam = stage(buf, F.lam.data(), F.lam.size());
-    fo[f].lam_soff = stage(buf, F.lam_soff.data(), F.lam_soff.size());
-    fo[f].gsize = stage(buf, F.gsize.data(), F.gsize.size());
     fo[f].ometa = stage(buf, F.ometa.data(), F.ometa.size());
+    fo[f].unit_mask = stage(buf, F.unit_mask.data(), F.unit_mask.size());
+    fo[f].zrow = stage(buf, F.zrow.data(), F.zrow.size());
   }
   const size_t o_fcls = stage(buf, fdev.data(), fdev.size());
   const size_t o_fitems = stage(buf, fitems.data(), fitems.size());
@@ -389,32 +370,16 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     FastClassDev& D = fdev[f];
-    D.d = F.d; D.l = F.l; D.b = F.b; D.h = F.h; D.M = F.M; D.n3 = F.n3; D.nzi = F.nzi;
-    D.Ysize = F.Ysize; D.lam_ublock = F.lam_ublock;
-    const size_t NC = (size_t)1 << F.PC;
-    // region B data: raw-tile transposes | S2 (+ one spare row per thread) | Y
-    size_t data = std::max<size_t>(((size_t)F.P2 + 1) * NC * sweep_elem_bytes(prec) +
-                                       (size_t)kFastThreads * sweep_elem_bytes(prec),
-                                   (size_t)F.Ysize * 8);
-    data = std::max<size_t>(data, ((size_t)1 << F.b) * (prec == PREC_F32 ? 4 : 8));
-    D.tabo = (int32_t)((data + 255) & ~(size_t)255);
-    const size_t tab_ints = 256 + 16 + NC + 8 + 8;
-    D.lamo = (int32_t)((tab_ints * 4 + 15) & ~(size_t)15);
-    const size_t need = fast_regA_bytes(prec, F.nzi) + D.tabo + D.lamo + (size_t)F.lam_ublock * 8;
-    if (need > 160 * 1024) {
-      free_batch(P);
-      return fail(FSI_ERR_INTERNAL, "register-phase kernel does not fit in LDS");
-    }
-    fast_lds = std::max(fast_lds, need);
-    D.u3tab = reinterpret_cast<const int32_t*>(A + fo[f].u3tab);
-    D.unit_s = reinterpret_cast<const int32_t*>(A + fo[f].unit_s);
-    D.row2 = reinterpret_cast<const int32_t*>(A + fo[f].row2);
-    D.zbase = reinterpret_cast<const int32_t*>(A + fo[f].zbase);
-    D.ytab = reinterpret_cast<const uint32_t*>(A + fo[f].ytab);
+    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M;
+    fast_lds = std::max(fast_lds, fast_lds_bytes(prec, F.l));
     D.lam = reinterpret_cast<const double*>(A + fo[f].lam);
-    D.lam_soff = reinterpret_cast<const int32_t*>(A + fo[f].lam_soff);
-    D.gsize = reinterpret_cast<const int32_t*>(A + fo[f].gsize);
     D.ometa = reinterpret_cast<const uint32_t*>(A + fo[f].ometa);
+    D.unit_mask = reinterpret_cast<const int32_t*>(A + fo[f].unit_mask);
+    D.zrow = reinterpret_cast<const int32_t*>(A + fo[f].zrow);
+  }
+  if (fast_lds > 160 * 1024) {
+    free_batch(P);
+    return fail(FSI_ERR_INTERNAL, "register-phase kernel does not fit in LDS");
   }
   std::memcpy(buf.data() + o_fcls, fdev.data(), fdev.size() * sizeof(FastClassDev));
   // instance descriptors carry the fast fields filled above

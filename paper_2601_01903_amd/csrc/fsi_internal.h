@@ -34,39 +34,23 @@ struct ClassDev {
   const uint32_t* osh;      // [M] S_H (mask over the h high bits)
 };
 
-// Tables of the register-phase tile kernel (three in-register sweep phases
-// of PA, PB, PC sites; see fsi_fast.hip), as seen by the kernel.
-// Phase-3 units are the output prefixes sigma_AB over the first PA + PB
-// sites with |sigma_AB| <= l, sorted by |sigma_AB| (then by mask). Counter
-// states are stored by their counter RELATIVE to |sigma| (row r holds
-// t = |sigma| + r), so row r of every unit is one contiguous column block.
+// Tables of the register-phase tile kernel (fsi_tile11.hip): tiles of 11
+// low bits, l <= 4. The in-tile layouts are compile-time functions of l; the
+// tables here hold what depends on d (weights, output metadata) and the
+// per-thread unit maps of the sweep phases.
 struct FastClassDev {
-  int32_t d, l, b, h;
-  int32_t M;            // outputs per instance
-  int32_t n3;           // phase-3 units
-  int32_t nzi;          // final output prefixes S_L (Z columns, + 1 spare)
-  int32_t Ysize;        // per-tile partial results (padded to KY * threads)
-  int32_t lam_ublock;   // doubles per high-popcount block of relative weights
-  int32_t tabo;         // byte offset of the per-item LDS tables in region B
-  int32_t lamo;         // byte offset of the weight block from tabo
-  int32_t pad;
-  const int32_t* u3tab;     // [2^PA * 2^PB] unit of sigma_A | sigma_B << PA, or n3
-  const int32_t* unit_s;    // [n3] |sigma_AB|
-  const int32_t* row2;      // [PA+PB+1] first S2 row of relative counter r
-  const int32_t* zbase;     // [2^PC] first Z column of sigma_C
-  const uint32_t* ytab;     // [Ysize] Z column | s_L << 16 | slot << 21
-  const double* lam;        // [(h+1) * lam_ublock] weights by relative counter
-  const int32_t* lam_soff;  // [l+1]
-  const int32_t* gsize;     // [l+1] number of S_L with |S_L| = s
-  const uint32_t* ometa;    // [M] Y index of (S_L, s_H, j = 0) | s_L << 16 | S_H << 19
+  int32_t d, l, h, M;
+  const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
+  const uint32_t* ometa;      // [M] Y index | C(11, s_L) << 11 | S_H << 20
+  const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
+  const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
 };
 
 struct FastClassHost {
-  int d = 0, l = 0, b = 0, h = 0, PA = 0, PB = 0, PC = 0;
-  int M = 0, n3 = 0, nzi = 0, Ysize = 0, Yreal = 0, lam_ublock = 0, P2 = 0, nZ = 0;
-  std::vector<int32_t> u3tab, unit_s, row2, zbase, lam_soff, gsize;
-  std::vector<uint32_t> ytab, ometa;
+  int d = 0, l = 0, h = 0, M = 0;
   std::vector<double> lam;
+  std::vector<uint32_t> ometa;
+  std::vector<int32_t> unit_mask, zrow;
 };
 
 struct InstDev {
@@ -101,10 +85,8 @@ double weight_full(int s, int t, int l);
 int64_t sweep_peak_entries(int b, int l);
 // Builds all tables for one class; returns "" or an error message.
 std::string build_class(int d, int l, int b, int algo, ClassHost* out);
-// Builds the register-phase kernel tables (fused algorithm) for a tile of
-// PA + PB + PC low bits; the final weights come from an already built class
-// with the same (d, l, b).
-std::string build_fast_class(const ClassHost& C, int PA, int PB, int PC, int ypad,
-                             FastClassHost* out);
+// Builds the register-phase kernel tables from an already built fused class
+// with b = 11 and l <= 4 (its final weights and output order).
+std::string build_fast_class(const ClassHost& C, FastClassHost* out);
 
 }  // namespace fsi

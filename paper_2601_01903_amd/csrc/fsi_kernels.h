@@ -19,10 +19,11 @@ struct MobItem {
   int64_t block;            // (bits above the group) * 2^(lo-cb) + low chunk
 };
 
-// Register-phase kernel (fsi_fast.hip)
+// Register-phase kernel (fsi_tile11.hip)
 constexpr int kFastThreads = 256;
 constexpr int kFastKmax = 25;      // outputs per thread: M <= 25 * 256
-constexpr int kFastKy = 6;         // final-core entries per thread: Ysize <= 6 * 256 (padded)
+constexpr int kFastTileBits = 11;
+constexpr int kFastMaxL = 4;
 
 struct FastItem {
   int32_t inst, tb, te, pad;       // tiles [tb, te) of the instance's tile order
@@ -45,10 +46,9 @@ struct FastLaunch {
 
 hipError_t configure_fast(int prec, size_t lds);
 hipError_t launch_fast(const FastLaunch& f, hipStream_t st);
-int fast_pc(int prec);
 bool fast_supported(int prec);
-// LDS bytes of region A (phase-1 / final states) for a precision.
-size_t fast_regA_bytes(int prec, int nzi);
+// Dynamic LDS of the register-phase kernel for items of order l.
+size_t fast_lds_bytes(int prec, int l);
 
 struct LaunchArgs {
   int prec, algo;

@@ -7,6 +7,7 @@
 #include <map>
 
 #include "fsi_internal.h"
+#include "fsi_tile11.h"
 
 namespace fsi {
 
@@ -221,104 +222,56 @@ std::string build_class(int d, int l, int b, int algo, ClassHost* C) {
   return "";
 }
 
-std::string build_fast_class(const ClassHost& C, int PA, int PB, int PC, int ypad,
-                             FastClassHost* F) {
+std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
+  using namespace t11;
   const int l = C.l, b = C.b, h = C.h;
-  if (PA + PB + PC != b) return "phase split does not match the tile";
+  if (b != B) return "register-phase kernel needs 11-bit tiles";
   if (C.algo != ALGO_FUSED) return "register-phase kernel needs the fused algorithm";
-  if (h > 12) return "too many high bits for the register-phase kernel";
-  F->d = C.d; F->l = l; F->b = b; F->h = h; F->PA = PA; F->PB = PB; F->PC = PC;
-  F->M = C.M;
-  const int nA = 1 << PA, nB = 1 << PB, nC = 1 << PC;
-  const int kAB = PA + PB;
-  // phase-3 units: sigma_AB with |sigma_AB| <= l, sorted by (|sigma|, mask)
-  std::vector<uint32_t> units;
-  for (int s = 0; s <= l; ++s)
-    for (uint32_t m = 0; m < (uint32_t)(nA * nB); ++m)
-      if (popc(m) == s) units.push_back(m);
-  F->n3 = (int)units.size();
-  std::vector<int> unit_of(nA * nB, F->n3);
-  F->unit_s.resize(F->n3);
-  for (int u = 0; u < F->n3; ++u) {
-    unit_of[units[u]] = u;
-    F->unit_s[u] = popc(units[u]);
-  }
-  F->u3tab.assign(nA * nB, F->n3);
-  for (int sA = 0; sA < nA; ++sA)
-    for (int sB = 0; sB < nB; ++sB) F->u3tab[sA * nB + sB] = unit_of[sA | (sB << PA)];
-  // S2 rows: relative counter r in [0, kAB - |sigma_AB|]; row r holds the
-  // units with |sigma_AB| <= kAB - r, i.e. a prefix of the unit list
-  F->row2.assign(kAB + 1, 0);
-  int rows = 0;
-  for (int r = 0; r <= kAB; ++r) {
-    F->row2[r] = rows;
-    for (int u = 0; u < F->n3; ++u) if (F->unit_s[u] <= kAB - r) ++rows;
-  }
-  F->P2 = rows;
-  // Z columns: for each sigma_C the units with |sigma_AB| + |sigma_C| <= l
-  // (a prefix of the unit list); row r of a column holds t = s_L + r
-  F->zbase.assign(nC, 0);
-  int nzi = 0;
-  std::vector<std::pair<uint32_t, int>> finals;   // (S_L, Z column)
-  for (int sC = 0; sC < nC; ++sC) {
-    F->zbase[sC] = nzi;
-    for (int u = 0; u < F->n3; ++u)
-      if (F->unit_s[u] + popc(sC) <= l) {
-        finals.push_back({units[u] | ((uint32_t)sC << kAB), nzi});
-        ++nzi;
-      }
-  }
-  F->nzi = nzi + 1;  // one spare column for discarded writes
-  F->nZ = (b + 1) * F->nzi;
-  // partial results: groups (s_L, slot), each listing every S_L of that
-  // size in Z-column order
-  auto nslot = [&](int sL) {
-    const int top = std::min(l - sL, h);
-    return top < 0 ? 0 : (top + 1) * (top + 2) / 2;
-  };
-  std::vector<std::vector<std::pair<uint32_t, int>>> bys(l + 1);
-  for (auto& f : finals) bys[popc(f.first)].push_back(f);
-  F->gsize.assign(l + 1, 0);
-  std::vector<std::vector<int>> gbase(l + 1);
-  std::map<uint32_t, int> pos;
-  F->ytab.clear();
-  for (int sL = 0; sL <= l; ++sL) {
-    F->gsize[sL] = (int)bys[sL].size();
-    for (size_t p = 0; p < bys[sL].size(); ++p) pos[bys[sL][p].first] = (int)p;
-    for (int sl = 0; sl < nslot(sL); ++sl) {
-      gbase[sL].push_back((int)F->ytab.size());
-      for (auto& f : bys[sL])
-        F->ytab.push_back((uint32_t)f.second | ((uint32_t)sL << 16) | ((uint32_t)sl << 21));
+  if (l > 4) return "register-phase kernel needs l <= 4";
+  if (h > kMaxH) return "too many high bits for the register-phase kernel";
+  F->d = C.d; F->l = l; F->h = h; F->M = C.M;
+  // phase-C units and their maps
+  const int nu = n3(l);
+  F->unit_mask.assign(nu, -1);
+  for (int sa = 0; sa < NA; ++sa)
+    for (int sb = 0; sb < NB; ++sb) {
+      const int u = unit_index(l, sa, sb);
+      if (u < 0) continue;
+      if (u >= nu || F->unit_mask[u] != -1) return "unit order is not a bijection";
+      F->unit_mask[u] = sa | (sb << PA);
     }
-  }
-  F->Yreal = (int)F->ytab.size();
-  if (F->Yreal + 1 > ypad) return "too many partial results for the register-phase kernel";
-  // padding entries: a spare Z column, weight block of s_L = 0, slot 0,
-  // written to Y slots the gather never reads
-  while ((int)F->ytab.size() < ypad) F->ytab.push_back((uint32_t)(F->nzi - 1));
-  F->Ysize = ypad;
-  // relative weights: lam_rel[u][s_L][slot][r] = lambda_u(s_L, slot, t = s_L + r)
-  F->lam_soff.assign(l + 1, 0);
-  int off = 0;
-  for (int sL = 0; sL <= l; ++sL) { F->lam_soff[sL] = off; off += nslot(sL) * (b + 1); }
-  F->lam_ublock = off;
-  F->lam.assign((size_t)(h + 1) * off, 0.0);
+  for (int u = 0; u < nu; ++u)
+    if (F->unit_mask[u] < 0) return "unit order has a hole";
+  F->zrow.assign((size_t)nu * NC, 0);
+  for (int u = 0; u < nu; ++u)
+    for (int sc = 0; sc < NC; ++sc)
+      F->zrow[(size_t)u * NC + sc] = zrow_of(l, (uint32_t)F->unit_mask[u] | ((uint32_t)sc << KAB));
+  // weights: entry (u, s_L, slot, r) = the class's precontracted weight of
+  // counter t = s_L + r (zero past t = 11 and for slots the class lacks)
+  const int lb = lamblock(l);
+  F->lam.assign((size_t)(h + 1) * lb, 0.0);
   for (int u = 0; u <= h; ++u)
-    for (int sL = 0; sL <= std::min(l, b); ++sL)
-      for (int sl = 0; sl < nslot(sL); ++sl)
-        for (int r = 0; sL + r <= b; ++r)
-          F->lam[(size_t)u * off + F->lam_soff[sL] + sl * (b + 1) + r] =
-              C.lam[(size_t)u * C.lam_ublock + C.lam_soff[sL] + sl * (b + 1) + sL + r];
-  // outputs: Y index of (S_L, s_H, j = 0); slot (s_H, j) sits j groups later
+    for (int sL = 0; sL <= l; ++sL) {
+      const int top = std::min(l - sL, h);
+      for (int sH = 0; sH <= top; ++sH)
+        for (int j = 0; j <= sH; ++j) {
+          const int slot = sH * (sH + 1) / 2 + j;
+          for (int r = 0; sL + r <= b; ++r)
+            F->lam[(size_t)u * lb + lamoff(l, sL) + slot * ZROW + r] =
+                C.lam[(size_t)u * C.lam_ublock + C.lam_soff[sL] + slot * (b + 1) + sL + r];
+        }
+    }
+  // outputs
   F->ometa.resize(C.out_masks.size());
   const uint32_t lowmask = (1u << b) - 1;
   for (size_t k = 0; k < C.out_masks.size(); ++k) {
     const uint32_t S = C.out_masks[k];
     const uint32_t SL = S & lowmask, SH = S >> b;
     const int sL = popc(SL), sH = popc(SH);
-    const int A = gbase[sL][sH * (sH + 1) / 2] + pos.at(SL);
-    if (A >= (1 << 16)) return "partial-result index too large";
-    F->ometa[k] = (uint32_t)A | ((uint32_t)sL << 16) | (SH << 19);
+    const uint32_t A = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) + rank_colex(SL));
+    const uint32_t G = (uint32_t)cbinom(B, sL);
+    if (A > kMetaA || G > kMetaG || SH >= (1u << kMaxH)) return "output metadata overflow";
+    F->ometa[k] = A | (G << kMetaGShift) | (SH << kMetaHShift);
   }
   return "";
 }

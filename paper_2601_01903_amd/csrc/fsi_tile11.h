@@ -1,0 +1,156 @@
+// Compile-time layout of the 2^11-value register-phase tile (fused algorithm,
+// l <= 4), shared by the kernel (fsi_tile11.hip) and the host tables
+// (fsi_tables.cpp). Everything here depends only on l: the tile splits its
+// 11 low bits into phase A (bits 0-3), phase B (bits 4-7), phase C (bits 8-10).
+//
+// Counter states are stored by their counter RELATIVE to the popcount of
+// their output prefix sigma (entry r holds t = |sigma| + r), so an output
+// prefix owns the entries r = 0 .. (sites so far) - |sigma|.
+//
+//  S1  phase-A states (sigma_A, r): row off1(r) + rankA(sigma_A), one column
+//      per phase-B/C input (b + 16 c); a row is padded by one 16-byte chunk.
+//  S2  phase-B states (sigma_AB, i): for each relative counter i and each
+//      half of the 8 phase-C inputs, one 4-input chunk per unit sigma_AB
+//      (|sigma_AB| <= l); entries past a unit's counter range hold zeros.
+//  Z   final states (S_L, r), one row of 12 entries per S_L; rows grouped by
+//      |S_L| and ranked in colex order inside a group; one dump row.
+//  Y   per-tile partial results Y[S_L, s_H, j]: group (s_L, slot) holds every
+//      S_L of that size in rank order; slot = s_H (s_H + 1) / 2 + j.
+#pragma once
+#include <cstdint>
+
+namespace fsi {
+namespace t11 {
+
+constexpr int PA = 4, PB = 4, PC = 3, B = 11;
+constexpr int NA = 1 << PA, NB = 1 << PB, NC = 1 << PC;
+constexpr int KAB = PA + PB;
+constexpr int NT = 256;      // threads per workgroup
+constexpr int ZROW = 12;     // entries per Z row (B + 1)
+
+constexpr int cbinom(int n, int k) {
+  if (k < 0 || n < 0 || k > n) return 0;
+  long r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return (int)r;
+}
+constexpr int cpop(int x) {
+  int c = 0;
+  while (x) { c += x & 1; x >>= 1; }
+  return c;
+}
+// 4-bit masks in (popcount, value) order
+constexpr int orderA(int k) {
+  int idx = 0;
+  for (int s = 0; s <= 4; ++s)
+    for (int m = 0; m < 16; ++m)
+      if (cpop(m) == s) {
+        if (idx == k) return m;
+        ++idx;
+      }
+  return -1;
+}
+constexpr int rankA(int mask) {
+  int idx = 0;
+  for (int s = 0; s <= 4; ++s)
+    for (int m = 0; m < 16; ++m)
+      if (cpop(m) == s) {
+        if (m == mask) return idx;
+        ++idx;
+      }
+  return -1;
+}
+// orderA(k) for a run-time k: nibble k of this constant
+constexpr uint64_t kOrderANibbles = 0xfedb7ca965384210ull;
+// number of 4-bit masks with popcount <= m
+constexpr int N4(int m) {
+  int n = 0;
+  for (int s = 0; s <= m && s <= 4; ++s) n += cbinom(4, s);
+  return n;
+}
+// colex rank of a mask among the masks of the same popcount
+constexpr int rank_colex(uint32_t mask) {
+  int r = 0, k = 0;
+  for (int p = 0; p < 32; ++p)
+    if ((mask >> p) & 1u) {
+      r += cbinom(p, k + 1);
+      ++k;
+    }
+  return r;
+}
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+
+// ---- S1 ----
+constexpr int off1(int L, int r) {
+  int o = 0;
+  for (int q = 0; q < r; ++q) o += N4(imin(L, PA - q));
+  return o;
+}
+constexpr int rows1(int L) { return off1(L, PA + 1); }
+template <typename T> constexpr int row1_stride() { return 128 + 16 / (int)sizeof(T); }
+
+// ---- phase-C units sigma_AB = sigma_A | sigma_B << 4, |sigma_AB| <= L,
+// ordered by sigma_B, then rankA(sigma_A): the valid sigma_A of a sigma_B
+// are a prefix of the rankA order, so unit = ubase(sigma_B) + rankA ----
+constexpr int ubase(int L, int sb) {
+  int u = 0;
+  for (int q = 0; q < sb; ++q) u += N4(L - cpop(q));
+  return u;
+}
+constexpr int n3(int L) { return ubase(L, NB); }
+constexpr int unit_index(int L, int sa, int sb) {
+  return cpop(sa) + cpop(sb) > L ? -1 : ubase(L, sb) + rankA(sa);
+}
+// element (i, unit, c) at ((2 i + c / 4) * n3 + unit) * 4 + c % 4
+constexpr int s2_elems(int L) { return (KAB + 1) * n3(L) * NC; }
+
+// ---- Z rows ----
+constexpr int zbase(int s) {
+  int o = 0;
+  for (int q = 0; q < s; ++q) o += cbinom(B, q);
+  return o;
+}
+constexpr int nzrows(int L) { return zbase(L + 1); }        // the dump row follows
+constexpr int zrow_of(int L, uint32_t SL) {
+  const int s = cpop((int)SL);
+  return s > L ? nzrows(L) : zbase(s) + rank_colex(SL);
+}
+
+// ---- Y ----
+constexpr int nslots(int L, int s) { return s > L ? 0 : (L - s + 1) * (L - s + 2) / 2; }
+constexpr int ybase(int L, int s) {
+  int o = 0;
+  for (int q = 0; q < s; ++q) o += nslots(L, q) * cbinom(B, q);
+  return o;
+}
+constexpr int ysize(int L) { return ybase(L, L + 1); }
+
+// ---- final-core weights (FP64, global memory), per high popcount u:
+// entry (s_L, slot, r) at lamoff(s_L) + slot * 12 + r (zero for r > 11 - s_L) ----
+constexpr int lamoff(int L, int s) {
+  int o = 0;
+  for (int q = 0; q < s; ++q) o += nslots(L, q) * ZROW;
+  return o;
+}
+constexpr int lamblock(int L) { return lamoff(L, L + 1); }
+
+// ---- weight-core work of one tile: 64-lane tasks. For |S_L| >= 2 a lane
+// owns one Z row and computes all its slots; the (|S_L| <= 1) rows are few,
+// so there a lane owns one (row, slot) pair ----
+constexpr int row_tasks(int s) { return (cbinom(B, s) + 63) / 64; }
+constexpr int npairs(int L) {
+  int n = 0;
+  for (int s = 0; s <= imin(1, L); ++s) n += cbinom(B, s) * nslots(L, s);
+  return n;
+}
+constexpr int ntasks(int L) {
+  int n = (npairs(L) + 63) / 64;
+  for (int s = 2; s <= L; ++s) n += row_tasks(s);
+  return n;
+}
+// meta word of an output: Y index of (S_L, s_H, j = 0) | C(11, |S_L|) << 11 | S_H << 20
+constexpr uint32_t kMetaA = 0x7FF, kMetaG = 0x1FF;
+constexpr int kMetaGShift = 11, kMetaHShift = 20, kMaxH = 12;
+
+}  // namespace t11
+}  // namespace fsi

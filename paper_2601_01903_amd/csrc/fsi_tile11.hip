@@ -1,0 +1,559 @@
+// Register-phase tile kernel of the fused FSI algorithm (gfx950), tiles of
+// 2^11 values, l <= 4.
+//
+// A workgroup of 256 threads owns a work item: a run of tiles of one
+// instance (raw v, high index U_H). Per tile it computes
+//   - the in-tile Moebius butterfly (Sec. 3.2) over the 11 low bits: bits
+//     8-10 in registers straight from the coalesced loads, bits 4-7 and 0-3
+//     through two LDS transposes;
+//   - the left-to-right counter sweep (Sec. 4.3 - 4.4) in three phases of 4,
+//     4 and 3 sites. Within a phase a thread owns one output prefix with all
+//     its counters and the phase's 2^P inputs in registers and walks the
+//     phase's output bits depth first: each output state adds its tau = 0
+//     and tau = 1 predecessors (the sparse MPO cores). Between phases the
+//     (sigma, t) states go through LDS, truncated to |sigma| <= l (the
+//     compressed output prefix);
+//   - the final weight core with the Moebius cores of the high sites
+//     precontracted into it (Sec. 4.5 applied to the high sites), in FP64:
+//     Y[S_L, s_H, j] = sum_t lambda_u(s_L + s_H, t, s_H + u - j) Z[S_L, t],
+//     u = |U_H|, the weights read through the scalar cache;
+//   - the cross-tile sum E_S += Y[S_L, |S_H|, |S_H & U_H|] in FP64 registers.
+// At the end of the item the FP64 partial sums go to a workspace; the
+// reduction kernel adds the items of an instance in a fixed order.
+//
+// Every LDS layout is a compile-time function of l (fsi_tile11.h), so the
+// hot loops address LDS with one per-thread base register and immediate
+// offsets. LDS is used in two regions that alias across the phases:
+//   region 1: raw-tile transposes -> phase-B states S2 -> partial results Y
+//   region 2: phase-A states S1 -> final states Z
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "fsi_kernels.h"
+#include "fsi_tile11.h"
+
+namespace fsi {
+namespace t11 {
+
+// ----------------------------------------------------------------- numerics
+struct TwoF {
+  float hi, lo;
+};
+// TwoSum of the high parts plus the low parts, renormalised (Dekker's
+// double-length arithmetic)
+__device__ __forceinline__ TwoF sub(TwoF a, TwoF b) {
+  const float s = a.hi - b.hi;
+  const float bb = s - a.hi;
+  const float e = (a.hi - (s - bb)) + (-b.hi - bb);
+  const float t = e + (a.lo - b.lo);
+  const float hi = s + t;
+  return TwoF{hi, t - (hi - s)};
+}
+__device__ __forceinline__ float sub(float a, float b) { return a - b; }
+__device__ __forceinline__ double sub(double a, double b) { return a - b; }
+
+template <typename M> __device__ __forceinline__ M mob_from(float x);
+template <> __device__ __forceinline__ float mob_from<float>(float x) { return x; }
+template <> __device__ __forceinline__ double mob_from<double>(float x) { return x; }
+template <> __device__ __forceinline__ TwoF mob_from<TwoF>(float x) { return TwoF{x, 0.f}; }
+template <typename M> __device__ __forceinline__ M mob_from_d(double x);
+template <> __device__ __forceinline__ double mob_from_d<double>(double x) { return x; }
+
+template <typename S> __device__ __forceinline__ S to_sw(float x) { return (S)x; }
+template <typename S> __device__ __forceinline__ S to_sw(double x) { return (S)x; }
+template <typename S> __device__ __forceinline__ S to_sw(TwoF x);
+template <> __device__ __forceinline__ float to_sw<float>(TwoF x) { return x.hi + x.lo; }
+template <> __device__ __forceinline__ double to_sw<double>(TwoF x) {
+  return (double)x.hi + (double)x.lo;
+}
+
+// ------------------------------------------------- in-register counter sweep
+// Node of the depth-first walk over the output bits of one phase: X[t][r]
+// holds the states with counter t in [LO, LO + RC) for the 2^REM inputs r of
+// the bits still to consume. The most significant remaining bit is consumed
+// first: the sigma = 1 child keeps the tau = 1 half with t + 1; the sigma = 0
+// child adds the tau = 0 half at t and the tau = 1 half at t - 1. At a leaf
+// SIG is the output mask over the phase's bits and X[i] holds counter LO + i,
+// i.e. the counter relative to the prefix's popcount (LO = |SIG|).
+template <int REM, int LO, int RC, int SIG, typename T, typename Emit>
+__device__ __forceinline__ void rsweep(const T (&X)[RC][1 << REM], Emit& emit) {
+  if constexpr (REM == 0) {
+    emit.template leaf<SIG, LO, RC>(X);
+  } else {
+    constexpr int H = 1 << (REM - 1);
+    {
+      T Y0[RC + 1][H];
+#pragma unroll
+      for (int r = 0; r < H; ++r) {
+        Y0[0][r] = X[0][r];
+#pragma unroll
+        for (int t = 1; t < RC; ++t) Y0[t][r] = X[t][r] + X[t - 1][H + r];
+        Y0[RC][r] = X[RC - 1][H + r];
+      }
+      rsweep<REM - 1, LO, RC + 1, SIG>(Y0, emit);
+    }
+    {
+      T Y1[RC][H];
+#pragma unroll
+      for (int t = 0; t < RC; ++t)
+#pragma unroll
+        for (int r = 0; r < H; ++r) Y1[t][r] = X[t][H + r];
+      rsweep<REM - 1, LO + 1, RC, SIG | H>(Y1, emit);
+    }
+  }
+}
+
+// Raw-tile transposes: element (a, b, c) of the tile (index a + 16 b + 256 c)
+// at row (b + c) & 15, 16-byte chunk swizzled with row >> 2 (conflict-free
+// for the column and row accesses of the two butterfly steps).
+__device__ __forceinline__ int r_addr(int a, int b, int c) {
+  const int row = (b + c) & 15;
+  return (c << 8) + (row << 4) + ((((a >> 2) ^ (row >> 2)) & 3) << 2) + (a & 3);
+}
+
+// Weights are read-only for the whole launch: addressed through the constant
+// address space, so wave-uniform reads become scalar loads.
+typedef const __attribute__((address_space(4))) double* cdptr;
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; static constexpr int n = 4; };
+template <> struct Vec4<double> { using type = double2; static constexpr int n = 2; };
+
+// Compile-time tables of one order l (indexed with unrolled loop counters,
+// so every use folds into an immediate).
+struct A5 { int v[PA + 1]; };
+struct A16 { int v[16]; };
+constexpr A5 mk_off1(int L) {
+  A5 a{};
+  for (int r = 0; r <= PA; ++r) a.v[r] = off1(L, r);
+  return a;
+}
+constexpr A16 mk_ubase(int L) {
+  A16 a{};
+  for (int b = 0; b < NB; ++b) a.v[b] = ubase(L, b);
+  return a;
+}
+constexpr A16 mk_rank() {
+  A16 a{};
+  for (int m = 0; m < NA; ++m) a.v[m] = rankA(m);
+  return a;
+}
+template <int L>
+struct K {
+  static constexpr A5 off1v = mk_off1(L);
+  static constexpr A16 ub = mk_ubase(L);
+  static constexpr A16 rk = mk_rank();
+  static constexpr int N3 = n3(L);
+  static constexpr int LB = lamblock(L);
+  static constexpr int NTASK = ntasks(L);
+  static constexpr int NPAIR = npairs(L);
+  static constexpr int LAM0 = lamoff(L, 0), LAM1 = lamoff(L, 1);
+  static constexpr int YB0 = ybase(L, 0), YB1 = ybase(L, 1);
+};
+
+// ----------------------------------------------------------------- emitters
+// Phase A -> S1 row off1(i) + rankA(sigma_A), column = this thread's input.
+template <typename SwT, int L>
+struct EmitS1 {
+  SwT* S1;   // already offset by the thread's column
+  template <int SIG, int LO, int RC>
+  __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
+    if constexpr (cpop(SIG) <= L) {
+      constexpr int R1 = row1_stride<SwT>();
+      constexpr int RK = K<L>::rk.v[SIG];
+#pragma unroll
+      for (int i = 0; i < RC; ++i) S1[(K<L>::off1v.v[i] + RK) * R1] = X[i][0];
+    }
+  }
+};
+
+// Phase B -> S2 entries (i, unit of (sigma_A, sigma_B), c): all 9 counters
+// (zeros past the leaf's), for the prefixes with |sigma_A| + |sigma_B| <= L.
+template <typename SwT, int L>
+struct EmitS2 {
+  SwT* S2;   // offset by ((c / 4) * n3 + rankA) * 4 + c % 4
+  int sA;
+  template <int SIG, int LO, int RC>
+  __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
+    constexpr int sB = cpop(SIG);
+    if constexpr (sB <= L) {
+      if (sA <= L - sB) {
+        constexpr int UB = K<L>::ub.v[SIG];
+        constexpr int N3 = K<L>::N3;
+#pragma unroll
+        for (int i = 0; i <= KAB; ++i) S2[(2 * i * N3 + UB) * 4] = i < RC ? X[i][0] : SwT(0);
+      }
+    }
+  }
+};
+
+// Phase C -> Z row of S_L = sigma_AB | sigma_C << 8 (12 entries, zero padded).
+template <typename SwT, int L>
+struct EmitZ {
+  SwT* Z;
+  const int (&zr)[NC];   // Z row per sigma_C (dump row where |S_L| > L)
+  int sAB;
+  template <int SIG, int LO, int RC>
+  __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
+    constexpr int sC = cpop(SIG);
+    if constexpr (sC <= L) {
+      if (sAB <= L - sC) {
+        using V = typename Vec4<SwT>::type;
+        constexpr int VN = Vec4<SwT>::n;
+        V* p = reinterpret_cast<V*>(Z + zr[SIG] * ZROW);
+#pragma unroll
+        for (int q = 0; q < ZROW / VN; ++q) {
+          SwT e[VN];
+#pragma unroll
+          for (int k = 0; k < VN; ++k) e[k] = q * VN + k < RC ? X[q * VN + k][0] : SwT(0);
+          if constexpr (VN == 4) p[q] = V{e[0], e[1], e[2], e[3]};
+          else p[q] = V{e[0], e[1]};
+        }
+      }
+    }
+  }
+};
+
+// --------------------------------------------------------------- LDS plan
+constexpr int align256(int x) { return (x + 255) & ~255; }
+constexpr int imax2(int a, int b) { return a > b ? a : b; }
+template <int L, typename SwT, typename MobT>
+struct Lds {
+  static constexpr int reg1 = align256(imax2(
+      imax2((int)(s2_elems(L) * sizeof(SwT)), (int)((1 << B) * sizeof(MobT))), ysize(L) * 8));
+  static constexpr int reg2 = align256(
+      imax2(rows1(L) * row1_stride<SwT>() * (int)sizeof(SwT),
+            (nzrows(L) + 1) * ZROW * (int)sizeof(SwT)));
+  static constexpr int bytes = reg1 + reg2;
+};
+
+// ------------------------------------------------------------ weight core
+// One task: 64 lanes, each owning one Z row of |S_L| = S (S >= 2) and
+// producing all its slots.
+template <int L, int S, typename SwT>
+__device__ __forceinline__ void row_task(int chunk, int lane, const SwT* Z, double* Y,
+                                         cdptr lamu) {
+  constexpr int NR = cbinom(B, S);
+  constexpr int RC = ZROW - S;
+  constexpr int NS = nslots(L, S);
+  constexpr int ZB = zbase(S), LO = lamoff(L, S), YB = ybase(L, S);
+  const int row = chunk * 64 + lane;
+  if (row >= NR) return;
+  const SwT* zr = Z + (ZB + row) * ZROW;
+  double z[RC];
+#pragma unroll
+  for (int r = 0; r < RC; ++r) z[r] = (double)zr[r];
+  cdptr lw = lamu + LO;
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    double a = 0.0;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) a = fma(lw[k * ZROW + r], z[r], a);
+    Y[YB + k * NR + row] = a;
+  }
+}
+
+// The (row, slot) pairs of |S_L| <= 1, 64 per task; per-lane weights.
+template <int L, typename SwT>
+__device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double* Y,
+                                          cdptr lamu) {
+  constexpr int N0 = nslots(L, 0), N1 = nslots(L, 1);
+  const int p = t * 64 + lane;
+  if (p >= K<L>::NPAIR) return;
+  int zrow, lofs, yidx;
+  if (p < N0) {
+    zrow = 0; lofs = K<L>::LAM0 + p * ZROW; yidx = K<L>::YB0 + p;
+  } else {
+    const int row = (p - N0) / N1, slot = (p - N0) - row * N1;
+    zrow = 1 + row; lofs = K<L>::LAM1 + slot * ZROW; yidx = K<L>::YB1 + slot * B + row;
+  }
+  const SwT* zr = Z + zrow * ZROW;
+  cdptr lw = lamu + lofs;
+  double a = 0.0;
+#pragma unroll
+  for (int r = 0; r < ZROW; ++r) a = fma(lw[r], (double)zr[r], a);
+  Y[yidx] = a;
+}
+
+template <int L, int S, typename SwT>
+__device__ __forceinline__ void lam_task(int t, int lane, const SwT* Z, double* Y,
+                                         cdptr lamu) {
+  if constexpr (S >= 2) {
+    constexpr int NTS = row_tasks(S);
+    static_assert(NTS > 0, "empty task group");
+    if (t < NTS) { row_task<L, S>(t, lane, Z, Y, lamu); return; }
+    lam_task<L, S - 1>(t - NTS, lane, Z, Y, lamu);
+  } else {
+    pair_task<L>(t, lane, Z, Y, lamu);
+  }
+}
+
+// ------------------------------------------------------------------ item
+template <int L, typename SwT, typename MobT, bool IN64>
+__device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, const InstDev& I,
+                                         const FastItem& W, const float* __restrict__ vals32,
+                                         const double* __restrict__ vals64,
+                                         const int32_t* __restrict__ torder,
+                                         double* __restrict__ partial, unsigned char* smem) {
+  constexpr int KMAX = kFastKmax;
+  constexpr int R1 = row1_stride<SwT>();
+  constexpr int N3 = K<L>::N3;
+  constexpr int LB = K<L>::LB;
+  constexpr int NTASK = K<L>::NTASK;
+  using LD = Lds<L, SwT, MobT>;
+  MobT* R = reinterpret_cast<MobT*>(smem);
+  SwT* S2 = reinterpret_cast<SwT*>(smem);
+  double* Y = reinterpret_cast<double*>(smem);
+  SwT* S1 = reinterpret_cast<SwT*>(smem + LD::reg1);
+  SwT* Z = reinterpret_cast<SwT*>(smem + LD::reg1);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int M = C->M;
+
+  // ---- per-item thread constants ----
+  // phase B: thread (rankA, c)
+  const int p2r = tid & 15, p2c = tid >> 4;
+  const int sA_mask = (int)((kOrderANibbles >> (4 * p2r)) & 15u);
+  const int sA = __popc(sA_mask);
+  const int wb = ((p2c >> 2) * N3 + p2r) * 4 + (p2c & 3);
+  // phase C: thread = unit
+  const int u3 = tid < N3 ? tid : 0;
+  const int sAB = __popc(C->unit_mask[u3]);
+  int zr[NC];
+#pragma unroll
+  for (int sc = 0; sc < NC; ++sc) zr[sc] = C->zrow[u3 * NC + sc];
+  // cross-tile sum
+  double acc[KMAX];
+  uint32_t meta[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int g = tid + k * NT;
+    acc[k] = 0.0;
+    meta[k] = g < M ? C->ometa[g] : 0u;
+  }
+
+  const int64_t vbase = I.voff;
+  MobT xr[NC];
+  auto load_tile = [&](int UH) {
+    const int64_t base = vbase + ((int64_t)UH << B) + tid;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if constexpr (IN64)
+        xr[c] = mob_from_d<MobT>(vals64[base + (c << 8)]);
+      else
+        xr[c] = mob_from<MobT>(vals32[base + (c << 8)]);
+    }
+  };
+  int UH = torder[I.tofs + W.tb];
+  load_tile(UH);
+
+  for (int k = W.tb; k < W.te; ++k) {
+    const int UHn = k + 1 < W.te ? torder[I.tofs + k + 1] : 0;
+    const int u = __builtin_amdgcn_readfirstlane(__popc(UH));
+    const cdptr lamu = (cdptr)(C->lam + (int64_t)u * LB);
+
+    // ---- Moebius over bits 8-10 in registers, then transpose ----
+#pragma unroll
+    for (int bit = 0; bit < PC; ++bit)
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (c & (1 << bit)) xr[c] = sub(xr[c], xr[c ^ (1 << bit)]);
+    {
+      const int a = tid & 15, b = tid >> 4;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) R[r_addr(a, b, c)] = xr[c];
+    }
+    __syncthreads();
+    // ---- Moebius over bits 4-7: thread (a, c) holds the 16 b values ----
+    if (tid < NA * NC) {
+      const int a = tid & 15, c = tid >> 4;
+      MobT y[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) y[b] = R[r_addr(a, b, c)];
+#pragma unroll
+      for (int bit = 0; bit < PB; ++bit)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+          if (b & (1 << bit)) y[b] = sub(y[b], y[b ^ (1 << bit)]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) R[r_addr(a, b, c)] = y[b];
+    }
+    __syncthreads();
+    // ---- Moebius over bits 0-3 + phase A: thread (b, c) holds the 16 a values ----
+    if (tid < NB * NC) {
+      const int b = tid & 15, c = tid >> 4;
+      MobT y[NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) y[a] = R[r_addr(a, b, c)];
+#pragma unroll
+      for (int bit = 0; bit < PA; ++bit)
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+          if (a & (1 << bit)) y[a] = sub(y[a], y[a ^ (1 << bit)]);
+      SwT X1[1][NA];
+#pragma unroll
+      for (int a = 0; a < NA; ++a) X1[0][a] = to_sw<SwT>(y[a]);
+      EmitS1<SwT, L> e1{S1 + tid};
+      rsweep<PA, 0, 1, 0>(X1, e1);
+    }
+    // prefetch the next tile while the sweep runs
+    if (k + 1 < W.te) load_tile(UHn);
+    __syncthreads();
+    // ---- phase B: thread (sigma_A, c), counters relative to |sigma_A| ----
+    if (tid < NA * NC && sA <= L) {
+      using V = typename Vec4<SwT>::type;
+      constexpr int VN = Vec4<SwT>::n;
+      SwT X2[PA + 1][NB];
+#pragma unroll
+      for (int r = 0; r <= PA; ++r) {
+        if (r <= PA - sA) {
+          const V* src = reinterpret_cast<const V*>(S1 + (K<L>::off1v.v[r] + p2r) * R1 + NB * p2c);
+#pragma unroll
+          for (int q = 0; q < NB / VN; ++q) {
+            const V v = src[q];
+            if constexpr (VN == 4) {
+              X2[r][4 * q] = v.x; X2[r][4 * q + 1] = v.y; X2[r][4 * q + 2] = v.z; X2[r][4 * q + 3] = v.w;
+            } else {
+              X2[r][2 * q] = v.x; X2[r][2 * q + 1] = v.y;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int b = 0; b < NB; ++b) X2[r][b] = SwT(0);
+        }
+      }
+      EmitS2<SwT, L> e2{S2 + wb, sA};
+      rsweep<PB, 0, PA + 1, 0>(X2, e2);
+    }
+    __syncthreads();
+    // ---- phase C: thread per unit sigma_AB, counters relative to |sigma_AB| ----
+    if (tid < N3) {
+      using V = typename Vec4<SwT>::type;
+      constexpr int VN = Vec4<SwT>::n;
+      SwT X3[KAB + 1][NC];
+#pragma unroll
+      for (int i = 0; i <= KAB; ++i) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const V* src = reinterpret_cast<const V*>(S2 + ((2 * i + h) * N3 + u3) * 4);
+#pragma unroll
+          for (int q = 0; q < 4 / VN; ++q) {
+            const V v = src[q];
+            if constexpr (VN == 4) {
+              X3[i][4 * h] = v.x; X3[i][4 * h + 1] = v.y; X3[i][4 * h + 2] = v.z; X3[i][4 * h + 3] = v.w;
+            } else {
+              X3[i][4 * h + 2 * q] = v.x; X3[i][4 * h + 2 * q + 1] = v.y;
+            }
+          }
+        }
+      }
+      EmitZ<SwT, L> ez{Z, zr, sAB};
+      rsweep<PC, 0, KAB + 1, 0>(X3, ez);
+    }
+    __syncthreads();
+    // ---- final weight core -> Y ----
+    for (int t = wave; t < NTASK; t += NT / 64) lam_task<L, L>(t, lane, Z, Y, lamu);
+    __syncthreads();
+    // ---- cross-tile sum: E_S += Y[S_L, s_H, |S_H & U_H|] ----
+#pragma unroll
+    for (int kk = 0; kk < KMAX; ++kk) {
+      const uint32_t m = meta[kk];
+      const int j = __popc((m >> kMetaHShift) & (uint32_t)UH);
+      acc[kk] += Y[(m & kMetaA) + j * ((m >> kMetaGShift) & kMetaG)];
+    }
+    UH = UHn;
+    __syncthreads();
+  }
+  double* P = partial + W.pofs;
+#pragma unroll
+  for (int kk = 0; kk < KMAX; ++kk) {
+    const int g = tid + kk * NT;
+    if (g < M) P[g] = acc[kk];
+  }
+}
+
+template <typename SwT, typename MobT, bool IN64>
+__global__ void __launch_bounds__(NT)
+tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
+              const FastItem* __restrict__ items, int n_items,
+              const float* __restrict__ vals32, const double* __restrict__ vals64,
+              const int32_t* __restrict__ torder, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const FastItem W = items[item];
+    const InstDev I = insts[W.inst];
+    const FastClassDev* C = classes + I.fcls;
+    switch (C->l) {
+      case 1: run_item<1, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 2: run_item<2, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 3: run_item<3, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      default: run_item<4, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename SwT, typename MobT>
+constexpr int lds_bytes_for(int L) {
+  return L == 1 ? Lds<1, SwT, MobT>::bytes
+       : L == 2 ? Lds<2, SwT, MobT>::bytes
+       : L == 3 ? Lds<3, SwT, MobT>::bytes
+                : Lds<4, SwT, MobT>::bytes;
+}
+
+}  // namespace t11
+
+// ------------------------------------------------------------------ launcher
+template <typename SwT, typename MobT, bool IN64>
+static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
+  auto k = t11::tile11_kernel<SwT, MobT, IN64>;
+  hipLaunchKernelGGL(k, dim3(f.grid), dim3(t11::NT), f.lds, st, f.classes, f.insts, f.items,
+                     f.n_items, static_cast<const float*>(f.vals32),
+                     static_cast<const double*>(f.vals64), f.torder, f.partial);
+  return hipGetLastError();
+}
+
+template <typename SwT, typename MobT, bool IN64>
+static hipError_t config_t11(size_t lds) {
+  auto k = t11::tile11_kernel<SwT, MobT, IN64>;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t configure_fast(int prec, size_t lds) {
+  switch (prec) {
+    case PREC_F32: return config_t11<float, float, false>(lds);
+    case PREC_F32_COMP: return config_t11<float, t11::TwoF, false>(lds);
+    case PREC_F32_FP64MOB: return config_t11<float, double, false>(lds);
+    case PREC_F64: return config_t11<double, double, true>(lds);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fast(const FastLaunch& f, hipStream_t st) {
+  switch (f.prec) {
+    case PREC_F32: return launch_t11<float, float, false>(f, st);
+    case PREC_F32_COMP: return launch_t11<float, t11::TwoF, false>(f, st);
+    case PREC_F32_FP64MOB: return launch_t11<float, double, false>(f, st);
+    case PREC_F64: return launch_t11<double, double, true>(f, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+bool fast_supported(int prec) {
+  return prec == PREC_F32 || prec == PREC_F32_COMP || prec == PREC_F32_FP64MOB ||
+         prec == PREC_F64;
+}
+
+size_t fast_lds_bytes(int prec, int l) {
+  switch (prec) {
+    case PREC_F32: return t11::lds_bytes_for<float, float>(l);
+    case PREC_F32_COMP: return t11::lds_bytes_for<float, t11::TwoF>(l);
+    case PREC_F32_FP64MOB: return t11::lds_bytes_for<float, double>(l);
+    case PREC_F64: return t11::lds_bytes_for<double, double>(l);
+  }
+  return 0;
+}
+
+}  // namespace fsi
