@@ -270,12 +270,27 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     insts[i].fcls = f;
     insts[i].tofs = tofs_of_fast[f];
     insts[i].pbase = ptot;
+    insts[i].pstride = F.nkk * kFastThreads;
     insts[i].nitems = (int32_t)((ntile + cs - 1) / cs);
     for (int64_t tb = 0; tb < ntile; tb += cs) {
       fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min(ntile, tb + cs), 0, ptot});
-      ptot += F.M;
+      ptot += (int64_t)F.nkk * kFastThreads;
     }
+  }  // one launch per order l: items grouped by l (stable, so each group keeps
+  // the instance order)
+  auto item_l = [&](const FastItem& it) { return P->fclasses[P->fast_of[P->cls_of[it.inst]]].l; };
+  std::stable_sort(fitems.begin(), fitems.end(),
+                   [&](const FastItem& x, const FastItem& y) { return item_l(x) < item_l(y); });
+  int lbeg[kFastMaxL + 2];
+  for (int l = 0; l <= kFastMaxL + 1; ++l) lbeg[l] = 0;
+  {
+    int cnt[kFastMaxL + 2] = {0};
+    for (const FastItem& it : fitems) ++cnt[item_l(it)];
+    int acc = 0;
+    for (int l = 1; l <= kFastMaxL; ++l) { lbeg[l] = acc; acc += cnt[l]; }
+    lbeg[kFastMaxL + 1] = acc;
   }
+
   // every tile of every instance (standalone Moebius low pass)
   std::vector<TileItem> all_tiles;
   for (int i = 0; i < n; ++i) {
@@ -327,12 +342,14 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
   std::vector<FastClassDev> fdev(P->fclasses.size());
-  struct FOffs { size_t lam, ometa, unit_mask, zrow; };
+  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx; };
   std::vector<FOffs> fo(P->fclasses.size());
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     fo[f].lam = stage(buf, F.lam.data(), F.lam.size());
-    fo[f].ometa = stage(buf, F.ometa.data(), F.ometa.size());
+    fo[f].meta = stage(buf, F.meta.data(), F.meta.size());
+    fo[f].gs8 = stage(buf, F.gs8.data(), F.gs8.size());
+    fo[f].pidx = stage(buf, F.pidx.data(), F.pidx.size());
     fo[f].unit_mask = stage(buf, F.unit_mask.data(), F.unit_mask.size());
     fo[f].zrow = stage(buf, F.zrow.data(), F.zrow.size());
   }
@@ -366,22 +383,27 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.osh = reinterpret_cast<const uint32_t*>(A + co[c].osh);
   }
   std::memcpy(buf.data() + o_cls, cdev.data(), cdev.size() * sizeof(ClassDev));
-  size_t fast_lds = 0;
+  size_t fast_lds[kFastMaxL + 1] = {0, 0, 0, 0, 0};
+  size_t fast_lds_max = 0;
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     FastClassDev& D = fdev[f];
-    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M;
-    fast_lds = std::max(fast_lds, fast_lds_bytes(prec, F.l));
+    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk;
+    fast_lds[F.l] = fast_lds_bytes(prec, F.l);
+    fast_lds_max = std::max(fast_lds_max, fast_lds[F.l]);
     D.lam = reinterpret_cast<const double*>(A + fo[f].lam);
-    D.ometa = reinterpret_cast<const uint32_t*>(A + fo[f].ometa);
+    D.meta = reinterpret_cast<const uint32_t*>(A + fo[f].meta);
+    D.gs8 = reinterpret_cast<const uint32_t*>(A + fo[f].gs8);
     D.unit_mask = reinterpret_cast<const int32_t*>(A + fo[f].unit_mask);
     D.zrow = reinterpret_cast<const int32_t*>(A + fo[f].zrow);
   }
-  if (fast_lds > 160 * 1024) {
+  if (fast_lds_max > 160 * 1024) {
     free_batch(P);
     return fail(FSI_ERR_INTERNAL, "register-phase kernel does not fit in LDS");
   }
   std::memcpy(buf.data() + o_fcls, fdev.data(), fdev.size() * sizeof(FastClassDev));
+  for (int i = 0; i < n; ++i)
+    if (insts[i].fast) insts[i].pidx = reinterpret_cast<const int32_t*>(A + fo[insts[i].fcls].pidx);
   // instance descriptors carry the fast fields filled above
   std::memcpy(buf.data() + o_inst, insts.data(), insts.size() * sizeof(InstDev));
   e = hipMemcpy(P->arena, buf.data(), buf.size(), hipMemcpyHostToDevice);
@@ -449,9 +471,12 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     a.fast.items = reinterpret_cast<const FastItem*>(A + o_fitems);
     a.fast.torder = reinterpret_cast<const int32_t*>(A + o_torder);
     a.fast.partial = P->partial;
-    a.fast.lds = fast_lds;
-    const int per_cu = std::max(1, (int)((160 * 1024) / fast_lds));
-    a.fast.grid = std::max(1, std::min<int>((int)fitems.size(), n_cu * per_cu));
+    for (int l = 0; l <= kFastMaxL + 1; ++l) a.fast.lbeg[l] = lbeg[l];
+    for (int l = 0; l <= kFastMaxL; ++l) {
+      a.fast.lds[l] = fast_lds[l];
+      const int nl = l >= 1 ? lbeg[l + 1] - lbeg[l] : 0;
+      a.fast.grid[l] = nl > 0 ? std::max(1, std::min(nl, n_cu * fast_wgs_per_cu(prec, l))) : 0;
+    }
   }
   *out = P;
   return FSI_OK;

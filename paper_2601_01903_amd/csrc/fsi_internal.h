@@ -38,19 +38,26 @@ struct ClassDev {
 // low bits, l <= 4. The in-tile layouts are compile-time functions of l; the
 // tables here hold what depends on d (weights, output metadata) and the
 // per-thread unit maps of the sweep phases.
+// Outputs are held by the kernel in slots: thread t owns the outputs
+// (kk, t), kk = 0 .. nkk-1; slot kk holds outputs of one |S_L| only, so the
+// stride between the j-variants of its partial results is uniform.
 struct FastClassDev {
   int32_t d, l, h, M;
+  int32_t nkk;                // slots per thread in use
+  int32_t pad;
   const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
-  const uint32_t* ometa;      // [M] Y index | C(11, s_L) << 11 | S_H << 20
+  const uint32_t* meta;       // [256 * kFastMetaStride] per thread: Y byte offset | S_H << 16
+  const uint32_t* gs8;        // [kFastMetaStride] byte stride between j-variants per slot
   const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
   const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
 };
 
 struct FastClassHost {
-  int d = 0, l = 0, h = 0, M = 0;
+  int d = 0, l = 0, h = 0, M = 0, nkk = 0;
   std::vector<double> lam;
-  std::vector<uint32_t> ometa;
+  std::vector<uint32_t> meta, gs8;
   std::vector<int32_t> unit_mask, zrow;
+  std::vector<int32_t> pidx;  // [M] slot index kk * 256 + t of canonical output k
 };
 
 struct InstDev {
@@ -61,10 +68,13 @@ struct InstDev {
   int64_t yoff;      // first partial result (doubles) in the Y workspace
   int64_t woff;      // first element of the Moebius workspace (two-pass)
   int32_t fast;      // 1: handled by the register-phase kernel
-  int32_t nitems;    // its work items (partial sums at pbase + j * M)
+  int32_t nitems;    // its work items (partial sums at pbase + j * pstride)
   int32_t tofs;      // first entry of its class's tile order
   int32_t fcls;      // index into the register-phase class array
   int64_t pbase;     // first partial sum (doubles)
+  int32_t pstride;   // partial sums per work item
+  int32_t pad2;
+  const int32_t* pidx;  // [M] position of canonical output k in an item's partial sums
 };
 
 // Host-side tables of one class (built once, uploaded into a device arena).

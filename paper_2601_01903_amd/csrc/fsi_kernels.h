@@ -21,7 +21,8 @@ struct MobItem {
 
 // Register-phase kernel (fsi_tile11.hip)
 constexpr int kFastThreads = 256;
-constexpr int kFastKmax = 25;      // outputs per thread: M <= 25 * 256
+constexpr int kFastKmax = 27;      // output slots per thread
+constexpr int kFastMetaStride = 28;  // per-thread metadata words (7 x 16 bytes)
 constexpr int kFastTileBits = 11;
 constexpr int kFastMaxL = 4;
 
@@ -30,25 +31,32 @@ struct FastItem {
   int64_t pofs;                    // partial sums of this item
 };
 
+// Work items are sorted by order l; items [lbeg[l], lbeg[l+1]) have order l
+// and go to the kernel compiled for that l (one launch per order present).
 struct FastLaunch {
   int prec;
   const FastClassDev* classes;
   const InstDev* insts;
   const FastItem* items;
   int n_items;
+  int lbeg[kFastMaxL + 2];
+  int grid[kFastMaxL + 1];
+  size_t lds[kFastMaxL + 1];
   const void* vals32;
   const void* vals64;
   const int32_t* torder;
   double* partial;
-  int grid;
-  size_t lds;
 };
 
-hipError_t configure_fast(int prec, size_t lds);
-hipError_t launch_fast(const FastLaunch& f, hipStream_t st);
+// lds[l]: dynamic LDS of the order-l kernel, 0 = not used by the plan.
+hipError_t configure_fast(int prec, const size_t* lds);
+hipError_t launch_fast_group(const FastLaunch& f, int l, hipStream_t st);
+// Orders l with work items, ascending; returns their number.
+int fast_groups(const FastLaunch& f, int* ls);
 bool fast_supported(int prec);
 // Dynamic LDS of the register-phase kernel for items of order l.
 size_t fast_lds_bytes(int prec, int l);
+int fast_wgs_per_cu(int prec, int l);
 
 struct LaunchArgs {
   int prec, algo;

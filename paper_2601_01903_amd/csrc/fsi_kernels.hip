@@ -191,10 +191,9 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
     const InstDev I = insts[lo];
     const int k = (int)(g - out_offset[lo]);
     if (I.fast) {
-      const int64_t M = out_offset[lo + 1] - out_offset[lo];
-      const double* P = partial + I.pbase + k;
+      const double* P = partial + I.pbase + I.pidx[k];
       double acc = 0.0;
-      for (int j = 0; j < I.nitems; ++j) acc += P[(int64_t)j * M];
+      for (int j = 0; j < I.nitems; ++j) acc += P[(int64_t)j * I.pstride];
       out[I.ooff + k] = (OutT)acc;
       continue;
     }
@@ -345,7 +344,7 @@ hipError_t configure_kernels(int prec, int algo, size_t tile_lds, size_t mob_lds
 int num_stages(const LaunchArgs& a) {
   // fused: [register-phase kernel], [generic tile kernel], reduce
   // two-pass: Moebius low pass, high passes, tile, reduce
-  if (a.algo == ALGO_FUSED) return (a.fast.n_items > 0) + (a.n_tile_items > 0) + 1;
+  if (a.algo == ALGO_FUSED) return fast_groups(a.fast, nullptr) + (a.n_tile_items > 0) + 1;
   return 3 + a.n_mob_passes;
 }
 
@@ -359,11 +358,15 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
                        static_cast<InT*>(a.out));
     return hipGetLastError();
   }
-  if (a.algo == ALGO_FUSED && a.fast.n_items > 0 && stage == 0) {
-    FastLaunch f = a.fast;
-    f.vals32 = a.values;
-    f.vals64 = a.values;
-    return launch_fast(f, st);
+  if (a.algo == ALGO_FUSED) {
+    int ls[kFastMaxL];
+    const int ng = fast_groups(a.fast, ls);
+    if (stage < ng) {
+      FastLaunch f = a.fast;
+      f.vals32 = a.values;
+      f.vals64 = a.values;
+      return launch_fast_group(f, ls[stage], st);
+    }
   }
   if (a.algo == ALGO_FUSED) {
     hipLaunchKernelGGL((tile_kernel<InT, MobT, SwT, true>), dim3(a.grid_tile), dim3(kTileThreads),

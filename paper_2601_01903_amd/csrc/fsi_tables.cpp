@@ -7,6 +7,7 @@
 #include <map>
 
 #include "fsi_internal.h"
+#include "fsi_kernels.h"
 #include "fsi_tile11.h"
 
 namespace fsi {
@@ -261,18 +262,35 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
                 C.lam[(size_t)u * C.lam_ublock + C.lam_soff[sL] + slot * (b + 1) + sL + r];
         }
     }
-  // outputs
-  F->ometa.resize(C.out_masks.size());
+  // outputs: slots grouped by |S_L| (descending), each output of a group
+  // at (slot kb + q / 256, thread q % 256) for its q-th position in
+  // canonical order
+  const size_t M = C.out_masks.size();
   const uint32_t lowmask = (1u << b) - 1;
-  for (size_t k = 0; k < C.out_masks.size(); ++k) {
-    const uint32_t S = C.out_masks[k];
-    const uint32_t SL = S & lowmask, SH = S >> b;
-    const int sL = popc(SL), sH = popc(SH);
-    const uint32_t A = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) + rank_colex(SL));
-    const uint32_t G = (uint32_t)cbinom(B, sL);
-    if (A > kMetaA || G > kMetaG || SH >= (1u << kMaxH)) return "output metadata overflow";
-    F->ometa[k] = A | (G << kMetaGShift) | (SH << kMetaHShift);
+  std::vector<std::vector<uint32_t>> byl(l + 1);
+  for (size_t k = 0; k < M; ++k) byl[popc(C.out_masks[k] & lowmask)].push_back((uint32_t)k);
+  F->meta.assign((size_t)kFastThreads * kFastMetaStride, 0u);
+  F->gs8.assign(kFastMetaStride, 0u);
+  F->pidx.assign(M, -1);
+  int kb = 0;
+  for (int sL = l; sL >= 0; --sL) {
+    const std::vector<uint32_t>& ks = byl[sL];
+    const int nslot = (int)((ks.size() + kFastThreads - 1) / kFastThreads);
+    if (kb + nslot > kFastKmax) return "too many output slots for the register-phase kernel";
+    for (int q = 0; q < nslot; ++q) F->gs8[kb + q] = (uint32_t)cbinom(B, sL) * 8u;
+    for (size_t q = 0; q < ks.size(); ++q) {
+      const uint32_t S = C.out_masks[ks[q]];
+      const uint32_t SL = S & lowmask, SH = S >> b;
+      const int sH = popc(SH);
+      const uint32_t A = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) + rank_colex(SL));
+      const int kk = kb + (int)(q / kFastThreads), t = (int)(q % kFastThreads);
+      if (A * 8 >= (1u << 16) || SH >= (1u << kMaxH)) return "output metadata overflow";
+      F->meta[(size_t)t * kFastMetaStride + kk] = (A * 8) | (SH << 16);
+      F->pidx[ks[q]] = kk * kFastThreads + t;
+    }
+    kb += nslot;
   }
+  F->nkk = kb;
   return "";
 }
 

@@ -148,9 +148,8 @@ constexpr int ntasks(int L) {
   for (int s = 2; s <= L; ++s) n += row_tasks(s);
   return n;
 }
-// meta word of an output: Y index of (S_L, s_H, j = 0) | C(11, |S_L|) << 11 | S_H << 20
-constexpr uint32_t kMetaA = 0x7FF, kMetaG = 0x1FF;
-constexpr int kMetaGShift = 11, kMetaHShift = 20, kMaxH = 12;
+// output metadata word: byte offset of Y(S_L, s_H, j = 0) | S_H << 16
+constexpr int kMaxH = 12;
 
 }  // namespace t11
 }  // namespace fsi

@@ -104,16 +104,17 @@ __device__ __forceinline__ void rsweep(const T (&X)[RC][1 << REM], Emit& emit) {
 }
 
 // Raw-tile transposes: element (a, b, c) of the tile (index a + 16 b + 256 c)
-// at row (b + c) & 15, 16-byte chunk swizzled with row >> 2 (conflict-free
-// for the column and row accesses of the two butterfly steps).
-__device__ __forceinline__ int r_addr(int a, int b, int c) {
-  const int row = (b + c) & 15;
-  return (c << 8) + (row << 4) + ((((a >> 2) ^ (row >> 2)) & 3) << 2) + (a & 3);
-}
+// at a + 17 b + 272 c. Affine in each coordinate, so every access is a
+// per-thread base plus an immediate; the three access patterns (fixed c,
+// fixed b, fixed a across a wave) hit distinct banks (fixed c: 3 of 64
+// banks shared).
+constexpr int RB = 17, RC_ = 272;
+constexpr int r_elems = RC_ * NC;
 
 // Weights are read-only for the whole launch: addressed through the constant
 // address space, so wave-uniform reads become scalar loads.
 typedef const __attribute__((address_space(4))) double* cdptr;
+typedef const __attribute__((address_space(4))) uint32_t* cdptr_u;
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; static constexpr int n = 4; };
@@ -220,46 +221,59 @@ constexpr int imax2(int a, int b) { return a > b ? a : b; }
 template <int L, typename SwT, typename MobT>
 struct Lds {
   static constexpr int reg1 = align256(imax2(
-      imax2((int)(s2_elems(L) * sizeof(SwT)), (int)((1 << B) * sizeof(MobT))), ysize(L) * 8));
+      imax2((int)(s2_elems(L) * sizeof(SwT)), (int)(r_elems * sizeof(MobT))), ysize(L) * 8));
   static constexpr int reg2 = align256(
       imax2(rows1(L) * row1_stride<SwT>() * (int)sizeof(SwT),
             (nzrows(L) + 1) * ZROW * (int)sizeof(SwT)));
-  static constexpr int bytes = reg1 + reg2;
+  static constexpr int reg3 = align256(lamblock(L) * 8);   // weights of the current |U_H|
+  static constexpr int bytes = reg1 + reg2 + reg3;
 };
 
 // ------------------------------------------------------------ weight core
+// The weights of the tile's |U_H| sit in LDS (lw), read at wave-uniform
+// addresses (broadcast).
 // One task: 64 lanes, each owning one Z row of |S_L| = S (S >= 2) and
 // producing all its slots.
 template <int L, int S, typename SwT>
 __device__ __forceinline__ void row_task(int chunk, int lane, const SwT* Z, double* Y,
-                                         cdptr lamu) {
+                                         const double* lam) {
   constexpr int NR = cbinom(B, S);
   constexpr int RC = ZROW - S;
   constexpr int NS = nslots(L, S);
   constexpr int ZB = zbase(S), LO = lamoff(L, S), YB = ybase(L, S);
   const int row = chunk * 64 + lane;
-  if (row >= NR) return;
-  const SwT* zr = Z + (ZB + row) * ZROW;
+  const bool ok = row < NR;
+  const SwT* zr = Z + (ZB + (ok ? row : 0)) * ZROW;
   double z[RC];
 #pragma unroll
   for (int r = 0; r < RC; ++r) z[r] = (double)zr[r];
-  cdptr lw = lamu + LO;
+  const double2* lw = reinterpret_cast<const double2*>(lam + LO);
+  double a[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) a[k] = 0.0;
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
-    double a = 0.0;
 #pragma unroll
-    for (int r = 0; r < RC; ++r) a = fma(lw[k * ZROW + r], z[r], a);
-    Y[YB + k * NR + row] = a;
+    for (int r = 0; r < RC; r += 2) {
+      const double2 w = lw[(k * ZROW + r) / 2];
+      a[k] = fma(w.x, z[r], a[k]);
+      if (r + 1 < RC) a[k] = fma(w.y, z[r + 1], a[k]);
+    }
+  }
+  if (ok) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) Y[YB + k * NR + row] = a[k];
   }
 }
 
 // The (row, slot) pairs of |S_L| <= 1, 64 per task; per-lane weights.
 template <int L, typename SwT>
 __device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double* Y,
-                                          cdptr lamu) {
+                                          const double* lam) {
   constexpr int N0 = nslots(L, 0), N1 = nslots(L, 1);
-  const int p = t * 64 + lane;
-  if (p >= K<L>::NPAIR) return;
+  const int p0 = t * 64 + lane;
+  const bool ok = p0 < K<L>::NPAIR;
+  const int p = ok ? p0 : 0;
   int zrow, lofs, yidx;
   if (p < N0) {
     zrow = 0; lofs = K<L>::LAM0 + p * ZROW; yidx = K<L>::YB0 + p;
@@ -268,23 +282,38 @@ __device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double*
     zrow = 1 + row; lofs = K<L>::LAM1 + slot * ZROW; yidx = K<L>::YB1 + slot * B + row;
   }
   const SwT* zr = Z + zrow * ZROW;
-  cdptr lw = lamu + lofs;
+  const double2* lw = reinterpret_cast<const double2*>(lam + lofs);
   double a = 0.0;
 #pragma unroll
-  for (int r = 0; r < ZROW; ++r) a = fma(lw[r], (double)zr[r], a);
-  Y[yidx] = a;
+  for (int r = 0; r < ZROW; r += 2) {
+    const double2 w = lw[r / 2];
+    a = fma(w.x, (double)zr[r], a);
+    // entry 11 of an |S_L| = 1 row lies past its counters (weight 0)
+    const double z1 = (r + 1 < ZROW - 1 || zrow == 0) ? (double)zr[r + 1] : 0.0;
+    a = fma(w.y, z1, a);
+  }
+  if (ok) Y[yidx] = a;
 }
 
 template <int L, int S, typename SwT>
 __device__ __forceinline__ void lam_task(int t, int lane, const SwT* Z, double* Y,
-                                         cdptr lamu) {
+                                         const double* lam) {
   if constexpr (S >= 2) {
     constexpr int NTS = row_tasks(S);
     static_assert(NTS > 0, "empty task group");
-    if (t < NTS) { row_task<L, S>(t, lane, Z, Y, lamu); return; }
-    lam_task<L, S - 1>(t - NTS, lane, Z, Y, lamu);
+    if (t < NTS) { row_task<L, S>(t, lane, Z, Y, lam); return; }
+    lam_task<L, S - 1>(t - NTS, lane, Z, Y, lam);
   } else {
-    pair_task<L>(t, lane, Z, Y, lamu);
+    pair_task<L>(t, lane, Z, Y, lam);
+  }
+}
+
+// The tasks of wave W (W, W + 4, ...), unrolled at compile time.
+template <int L, int W, int T, typename SwT>
+__device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, const double* lam) {
+  if constexpr (T < K<L>::NTASK) {
+    lam_task<L, L>(T, lane, Z, Y, lam);
+    lam_wave<L, W, T + NT / 64, SwT>(lane, Z, Y, lam);
   }
 }
 
@@ -299,17 +328,16 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   constexpr int R1 = row1_stride<SwT>();
   constexpr int N3 = K<L>::N3;
   constexpr int LB = K<L>::LB;
-  constexpr int NTASK = K<L>::NTASK;
   using LD = Lds<L, SwT, MobT>;
   MobT* R = reinterpret_cast<MobT*>(smem);
   SwT* S2 = reinterpret_cast<SwT*>(smem);
   double* Y = reinterpret_cast<double*>(smem);
   SwT* S1 = reinterpret_cast<SwT*>(smem + LD::reg1);
   SwT* Z = reinterpret_cast<SwT*>(smem + LD::reg1);
+  double* lamL = reinterpret_cast<double*>(smem + LD::reg1 + LD::reg2);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int M = C->M;
 
   // ---- per-item thread constants ----
   // phase B: thread (rankA, c)
@@ -320,18 +348,16 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   // phase C: thread = unit
   const int u3 = tid < N3 ? tid : 0;
   const int sAB = __popc(C->unit_mask[u3]);
-  int zr[NC];
-#pragma unroll
-  for (int sc = 0; sc < NC; ++sc) zr[sc] = C->zrow[u3 * NC + sc];
-  // cross-tile sum
+  const int32_t* zrow_u = C->zrow + u3 * NC;
+  // cross-tile sum (the output metadata is re-read per tile from L1/L2 so it
+  // holds no registers during the sweep phases)
   double acc[KMAX];
-  uint32_t meta[KMAX];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    const int g = tid + k * NT;
-    acc[k] = 0.0;
-    meta[k] = g < M ? C->ometa[g] : 0u;
-  }
+  for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
+  const uint4* meta_g = reinterpret_cast<const uint4*>(C->meta + tid * kFastMetaStride);
+  const cdptr_u gs8 = (cdptr_u)C->gs8;
+  const int nkk = C->nkk;
+  int u_prev = -1;
 
   const int64_t vbase = I.voff;
   MobT xr[NC];
@@ -351,7 +377,12 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   for (int k = W.tb; k < W.te; ++k) {
     const int UHn = k + 1 < W.te ? torder[I.tofs + k + 1] : 0;
     const int u = __builtin_amdgcn_readfirstlane(__popc(UH));
-    const cdptr lamu = (cdptr)(C->lam + (int64_t)u * LB);
+    if (u != u_prev) {
+      // tiles run in order of |U_H|: the weights change at most h + 1 times
+      const double* src = C->lam + (int64_t)u * LB;
+      for (int i = tid; i < LB; i += NT) lamL[i] = src[i];
+      u_prev = u;
+    }
 
     // ---- Moebius over bits 8-10 in registers, then transpose ----
 #pragma unroll
@@ -360,32 +391,32 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       for (int c = 0; c < NC; ++c)
         if (c & (1 << bit)) xr[c] = sub(xr[c], xr[c ^ (1 << bit)]);
     {
-      const int a = tid & 15, b = tid >> 4;
+      MobT* rp = R + (tid & 15) + RB * (tid >> 4);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) R[r_addr(a, b, c)] = xr[c];
+      for (int c = 0; c < NC; ++c) rp[RC_ * c] = xr[c];
     }
     __syncthreads();
     // ---- Moebius over bits 4-7: thread (a, c) holds the 16 b values ----
     if (tid < NA * NC) {
-      const int a = tid & 15, c = tid >> 4;
+      MobT* rp = R + (tid & 15) + RC_ * (tid >> 4);
       MobT y[NB];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) y[b] = R[r_addr(a, b, c)];
+      for (int b = 0; b < NB; ++b) y[b] = rp[RB * b];
 #pragma unroll
       for (int bit = 0; bit < PB; ++bit)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
           if (b & (1 << bit)) y[b] = sub(y[b], y[b ^ (1 << bit)]);
 #pragma unroll
-      for (int b = 0; b < NB; ++b) R[r_addr(a, b, c)] = y[b];
+      for (int b = 0; b < NB; ++b) rp[RB * b] = y[b];
     }
     __syncthreads();
     // ---- Moebius over bits 0-3 + phase A: thread (b, c) holds the 16 a values ----
     if (tid < NB * NC) {
-      const int b = tid & 15, c = tid >> 4;
+      const MobT* rp = R + RB * (tid & 15) + RC_ * (tid >> 4);
       MobT y[NA];
 #pragma unroll
-      for (int a = 0; a < NA; ++a) y[a] = R[r_addr(a, b, c)];
+      for (int a = 0; a < NA; ++a) y[a] = rp[a];
 #pragma unroll
       for (int bit = 0; bit < PA; ++bit)
 #pragma unroll
@@ -397,8 +428,6 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       EmitS1<SwT, L> e1{S1 + tid};
       rsweep<PA, 0, 1, 0>(X1, e1);
     }
-    // prefetch the next tile while the sweep runs
-    if (k + 1 < W.te) load_tile(UHn);
     __syncthreads();
     // ---- phase B: thread (sigma_A, c), counters relative to |sigma_A| ----
     if (tid < NA * NC && sA <= L) {
@@ -448,33 +477,66 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
           }
         }
       }
+      int zr[NC];
+#pragma unroll
+      for (int sc = 0; sc < NC; ++sc) zr[sc] = zrow_u[sc];
       EmitZ<SwT, L> ez{Z, zr, sAB};
       rsweep<PC, 0, KAB + 1, 0>(X3, ez);
     }
+    // prefetch the next tile and this tile's output metadata while the
+    // weight core runs
+    if (k + 1 < W.te) load_tile(UHn);
+    uint32_t meta[kFastMetaStride];
+#pragma unroll
+    for (int q = 0; q < kFastMetaStride / 4; ++q) {
+      const uint4 v = meta_g[q];
+      meta[4 * q] = v.x; meta[4 * q + 1] = v.y; meta[4 * q + 2] = v.z; meta[4 * q + 3] = v.w;
+    }
     __syncthreads();
     // ---- final weight core -> Y ----
-    for (int t = wave; t < NTASK; t += NT / 64) lam_task<L, L>(t, lane, Z, Y, lamu);
+    switch (wave) {
+      case 0: lam_wave<L, 0, 0, SwT>(lane, Z, Y, lamL); break;
+      case 1: lam_wave<L, 1, 1, SwT>(lane, Z, Y, lamL); break;
+      case 2: lam_wave<L, 2, 2, SwT>(lane, Z, Y, lamL); break;
+      default: lam_wave<L, 3, 3, SwT>(lane, Z, Y, lamL); break;
+    }
     __syncthreads();
     // ---- cross-tile sum: E_S += Y[S_L, s_H, |S_H & U_H|] ----
+    // slot kk holds outputs of one |S_L|: the j-stride gs8[kk] is uniform
+    {
+      const uint32_t UHs = (uint32_t)UH << 16;
+      const unsigned char* Yb = reinterpret_cast<const unsigned char*>(Y);
+      constexpr int GB = 9;   // outputs per batch of reads
 #pragma unroll
-    for (int kk = 0; kk < KMAX; ++kk) {
-      const uint32_t m = meta[kk];
-      const int j = __popc((m >> kMetaHShift) & (uint32_t)UH);
-      acc[kk] += Y[(m & kMetaA) + j * ((m >> kMetaGShift) & kMetaG)];
+      for (int k0 = 0; k0 < KMAX; k0 += GB) {
+        double v[GB];
+#pragma unroll
+        for (int q = 0; q < GB; ++q) {
+          if (k0 + q < KMAX) {
+            const uint32_t m = meta[k0 + q];
+            const uint32_t off = (m & 0xFFFFu) + (uint32_t)__popc(m & UHs) * gs8[k0 + q];
+            v[q] = *reinterpret_cast<const double*>(Yb + off);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < GB; ++q)
+          if (k0 + q < KMAX) acc[k0 + q] += v[q];
+      }
     }
     UH = UHn;
     __syncthreads();
   }
-  double* P = partial + W.pofs;
+  double* P = partial + W.pofs + tid;
 #pragma unroll
-  for (int kk = 0; kk < KMAX; ++kk) {
-    const int g = tid + kk * NT;
-    if (g < M) P[g] = acc[kk];
-  }
+  for (int kk = 0; kk < KMAX; ++kk)
+    if (kk < nkk) P[kk * NT] = acc[kk];
 }
 
-template <typename SwT, typename MobT, bool IN64>
-__global__ void __launch_bounds__(NT)
+// One kernel per order l (the items of a launch all have that order).
+// FP32 sweep: two workgroups per CU (2 waves per SIMD), so at most 256 VGPRs
+// per thread; the FP64 sweep's LDS allows one workgroup per CU.
+template <int L, typename SwT, typename MobT, bool IN64, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               const FastItem* __restrict__ items, int n_items,
               const float* __restrict__ vals32, const double* __restrict__ vals64,
@@ -483,13 +545,7 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
-    const FastClassDev* C = classes + I.fcls;
-    switch (C->l) {
-      case 1: run_item<1, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
-      case 2: run_item<2, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
-      case 3: run_item<3, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
-      default: run_item<4, SwT, MobT, IN64>(C, I, W, vals32, vals64, torder, partial, smem); break;
-    }
+    run_item<L, SwT, MobT, IN64>(classes + I.fcls, I, W, vals32, vals64, torder, partial, smem);
     __syncthreads();
   }
 }
@@ -505,40 +561,75 @@ constexpr int lds_bytes_for(int L) {
 }  // namespace t11
 
 // ------------------------------------------------------------------ launcher
-template <typename SwT, typename MobT, bool IN64>
+template <typename SwT> constexpr int wpe_for() { return sizeof(SwT) == 4 ? 2 : 1; }
+
+template <int L, typename SwT, typename MobT, bool IN64>
 static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
-  auto k = t11::tile11_kernel<SwT, MobT, IN64>;
-  hipLaunchKernelGGL(k, dim3(f.grid), dim3(t11::NT), f.lds, st, f.classes, f.insts, f.items,
-                     f.n_items, static_cast<const float*>(f.vals32),
+  const int ib = f.lbeg[L], n = f.lbeg[L + 1] - f.lbeg[L];
+  if (n <= 0) return hipSuccess;
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>()>;
+  hipLaunchKernelGGL(k, dim3(f.grid[L]), dim3(t11::NT), f.lds[L], st, f.classes, f.insts,
+                     f.items + ib, n, static_cast<const float*>(f.vals32),
                      static_cast<const double*>(f.vals64), f.torder, f.partial);
   return hipGetLastError();
 }
 
-template <typename SwT, typename MobT, bool IN64>
+template <int L, typename SwT, typename MobT, bool IN64>
 static hipError_t config_t11(size_t lds) {
-  auto k = t11::tile11_kernel<SwT, MobT, IN64>;
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>()>;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t configure_fast(int prec, size_t lds) {
-  switch (prec) {
-    case PREC_F32: return config_t11<float, float, false>(lds);
-    case PREC_F32_COMP: return config_t11<float, t11::TwoF, false>(lds);
-    case PREC_F32_FP64MOB: return config_t11<float, double, false>(lds);
-    case PREC_F64: return config_t11<double, double, true>(lds);
+template <typename SwT, typename MobT, bool IN64>
+static hipError_t launch_group_t(const FastLaunch& f, int l, hipStream_t st) {
+  switch (l) {
+    case 1: return launch_t11<1, SwT, MobT, IN64>(f, st);
+    case 2: return launch_t11<2, SwT, MobT, IN64>(f, st);
+    case 3: return launch_t11<3, SwT, MobT, IN64>(f, st);
+    case 4: return launch_t11<4, SwT, MobT, IN64>(f, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_fast(const FastLaunch& f, hipStream_t st) {
-  switch (f.prec) {
-    case PREC_F32: return launch_t11<float, float, false>(f, st);
-    case PREC_F32_COMP: return launch_t11<float, t11::TwoF, false>(f, st);
-    case PREC_F32_FP64MOB: return launch_t11<float, double, false>(f, st);
-    case PREC_F64: return launch_t11<double, double, true>(f, st);
+template <typename SwT, typename MobT, bool IN64>
+static hipError_t config_all_t(const size_t* lds) {
+  hipError_t e = hipSuccess;
+  if (lds[1] && (e = config_t11<1, SwT, MobT, IN64>(lds[1])) != hipSuccess) return e;
+  if (lds[2] && (e = config_t11<2, SwT, MobT, IN64>(lds[2])) != hipSuccess) return e;
+  if (lds[3] && (e = config_t11<3, SwT, MobT, IN64>(lds[3])) != hipSuccess) return e;
+  if (lds[4] && (e = config_t11<4, SwT, MobT, IN64>(lds[4])) != hipSuccess) return e;
+  return e;
+}
+
+hipError_t configure_fast(int prec, const size_t* lds) {
+  switch (prec) {
+    case PREC_F32: return config_all_t<float, float, false>(lds);
+    case PREC_F32_COMP: return config_all_t<float, t11::TwoF, false>(lds);
+    case PREC_F32_FP64MOB: return config_all_t<float, double, false>(lds);
+    case PREC_F64: return config_all_t<double, double, true>(lds);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_fast_group(const FastLaunch& f, int l, hipStream_t st) {
+  switch (f.prec) {
+    case PREC_F32: return launch_group_t<float, float, false>(f, l, st);
+    case PREC_F32_COMP: return launch_group_t<float, t11::TwoF, false>(f, l, st);
+    case PREC_F32_FP64MOB: return launch_group_t<float, double, false>(f, l, st);
+    case PREC_F64: return launch_group_t<double, double, true>(f, l, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+int fast_groups(const FastLaunch& f, int* ls) {
+  int n = 0;
+  for (int l = 1; l <= kFastMaxL; ++l)
+    if (f.lbeg[l + 1] > f.lbeg[l]) {
+      if (ls) ls[n] = l;
+      ++n;
+    }
+  return n;
 }
 
 bool fast_supported(int prec) {
@@ -554,6 +645,14 @@ size_t fast_lds_bytes(int prec, int l) {
     case PREC_F64: return t11::lds_bytes_for<double, double>(l);
   }
   return 0;
+}
+
+// Workgroups of the register-phase kernel that fit on one CU.
+int fast_wgs_per_cu(int prec, int l) {
+  const size_t lds = fast_lds_bytes(prec, l);
+  const int by_lds = lds ? (int)((160 * 1024) / lds) : 1;
+  const int by_regs = prec == PREC_F64 ? 1 : 2;
+  return std::max(1, std::min(by_lds, by_regs));
 }
 
 }  // namespace fsi
