@@ -348,7 +348,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   // phase C: thread = unit
   const int u3 = tid < N3 ? tid : 0;
   const int sAB = __popc(C->unit_mask[u3]);
-  const int32_t* zrow_u = C->zrow + u3 * NC;
+  int zr[NC];
+#pragma unroll
+  for (int sc = 0; sc < NC; ++sc) zr[sc] = C->zrow[u3 * NC + sc];
   // cross-tile sum (the output metadata is re-read per tile from L1/L2 so it
   // holds no registers during the sweep phases)
   double acc[KMAX];
@@ -477,9 +479,6 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
           }
         }
       }
-      int zr[NC];
-#pragma unroll
-      for (int sc = 0; sc < NC; ++sc) zr[sc] = zrow_u[sc];
       EmitZ<SwT, L> ez{Z, zr, sAB};
       rsweep<PC, 0, KAB + 1, 0>(X3, ez);
     }
