@@ -28,6 +28,7 @@
 //   region 2: phase-A states S1 -> final states Z
 #include <hip/hip_runtime.h>
 #include <cstdint>
+#include <type_traits>
 
 #include "fsi_kernels.h"
 #include "fsi_tile11.h"
@@ -39,15 +40,16 @@ namespace t11 {
 struct TwoF {
   float hi, lo;
 };
-// TwoSum of the high parts plus the low parts, renormalised (Dekker's
-// double-length arithmetic)
+// Two-float subtraction: Knuth's TwoSum of the high parts (exact error e),
+// the low parts and e added into the low word. The pair is not renormalised
+// (hi + lo still holds the value; the low word stays within a few ulps of the
+// operands over the 11 butterfly levels) and is rounded once, to FP32, when
+// the sweep takes it.
 __device__ __forceinline__ TwoF sub(TwoF a, TwoF b) {
   const float s = a.hi - b.hi;
   const float bb = s - a.hi;
   const float e = (a.hi - (s - bb)) + (-b.hi - bb);
-  const float t = e + (a.lo - b.lo);
-  const float hi = s + t;
-  return TwoF{hi, t - (hi - s)};
+  return TwoF{s, e + (a.lo - b.lo)};
 }
 __device__ __forceinline__ float sub(float a, float b) { return a - b; }
 __device__ __forceinline__ double sub(double a, double b) { return a - b; }
@@ -230,16 +232,15 @@ struct Lds {
 };
 
 // ------------------------------------------------------------ weight core
-// The weights of the tile's |U_H| sit in LDS (lw), read at wave-uniform
+// The weights of the tile's |U_H| sit in LDS (lam), read at wave-uniform
 // addresses (broadcast).
-// One task: 64 lanes, each owning one Z row of |S_L| = S (S >= 2) and
-// producing all its slots.
-template <int L, int S, typename SwT>
+// Row task: 64 lanes, each owning one Z row of |S_L| = S (S >= 2) and
+// producing the slots [K0, K1) of it.
+template <int L, int S, int K0, int K1, typename SwT>
 __device__ __forceinline__ void row_task(int chunk, int lane, const SwT* Z, double* Y,
                                          const double* lam) {
   constexpr int NR = cbinom(B, S);
   constexpr int RC = ZROW - S;
-  constexpr int NS = nslots(L, S);
   constexpr int ZB = zbase(S), LO = lamoff(L, S), YB = ybase(L, S);
   const int row = chunk * 64 + lane;
   const bool ok = row < NR;
@@ -248,25 +249,24 @@ __device__ __forceinline__ void row_task(int chunk, int lane, const SwT* Z, doub
 #pragma unroll
   for (int r = 0; r < RC; ++r) z[r] = (double)zr[r];
   const double2* lw = reinterpret_cast<const double2*>(lam + LO);
-  double a[NS];
+  double a[K1 - K0];
 #pragma unroll
-  for (int k = 0; k < NS; ++k) a[k] = 0.0;
-#pragma unroll
-  for (int k = 0; k < NS; ++k) {
+  for (int k = K0; k < K1; ++k) {
+    a[k - K0] = 0.0;
 #pragma unroll
     for (int r = 0; r < RC; r += 2) {
       const double2 w = lw[(k * ZROW + r) / 2];
-      a[k] = fma(w.x, z[r], a[k]);
-      if (r + 1 < RC) a[k] = fma(w.y, z[r + 1], a[k]);
+      a[k - K0] = fma(w.x, z[r], a[k - K0]);
+      if (r + 1 < RC) a[k - K0] = fma(w.y, z[r + 1], a[k - K0]);
     }
   }
   if (ok) {
 #pragma unroll
-    for (int k = 0; k < NS; ++k) Y[YB + k * NR + row] = a[k];
+    for (int k = K0; k < K1; ++k) Y[YB + k * NR + row] = a[k - K0];
   }
 }
 
-// The (row, slot) pairs of |S_L| <= 1, 64 per task; per-lane weights.
+// Pair task: the (row, slot) pairs of |S_L| <= 1, 64 per task; per-lane weights.
 template <int L, typename SwT>
 __device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double* Y,
                                           const double* lam) {
@@ -295,25 +295,51 @@ __device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double*
   if (ok) Y[yidx] = a;
 }
 
-template <int L, int S, typename SwT>
-__device__ __forceinline__ void lam_task(int t, int lane, const SwT* Z, double* Y,
-                                         const double* lam) {
-  if constexpr (S >= 2) {
-    constexpr int NTS = row_tasks(S);
-    static_assert(NTS > 0, "empty task group");
-    if (t < NTS) { row_task<L, S>(t, lane, Z, Y, lam); return; }
-    lam_task<L, S - 1>(t - NTS, lane, Z, Y, lam);
-  } else {
-    pair_task<L>(t, lane, Z, Y, lam);
+// Compile-time schedule of the weight-core tasks of one tile over the four
+// waves (longest task first to the least loaded wave). Row tasks of rows
+// with many slots are split into two slot ranges.
+struct LamTask { int kind, S, chunk, k0, k1, cost, wave; };
+struct LamPlan { LamTask t[40]; int n; };
+constexpr LamPlan make_lam_plan(int L) {
+  LamPlan p{};
+  p.n = 0;
+  for (int S = L; S >= 2; --S) {
+    const int RC = ZROW - S, NS = nslots(L, S);
+    for (int c = 0; c < row_tasks(S); ++c) {
+      const int parts = NS * RC > 40 ? 2 : 1;
+      for (int q = 0; q < parts; ++q) {
+        const int k0 = NS * q / parts, k1 = NS * (q + 1) / parts;
+        p.t[p.n++] = LamTask{0, S, c, k0, k1, (k1 - k0) * RC + RC + 8, -1};
+      }
+    }
   }
+  for (int c = 0; c < (npairs(L) + 63) / 64; ++c) p.t[p.n++] = LamTask{1, 0, c, 0, 0, 2 * ZROW + 8, -1};
+  int load[NT / 64] = {0, 0, 0, 0};
+  for (int done = 0; done < p.n; ++done) {
+    int best = -1;
+    for (int i = 0; i < p.n; ++i)
+      if (p.t[i].wave < 0 && (best < 0 || p.t[i].cost > p.t[best].cost)) best = i;
+    int w = 0;
+    for (int q = 1; q < NT / 64; ++q)
+      if (load[q] < load[w]) w = q;
+    p.t[best].wave = w;
+    load[w] += p.t[best].cost;
+  }
+  return p;
 }
+template <int L> struct LP { static constexpr LamPlan plan = make_lam_plan(L); };
 
-// The tasks of wave W (W, W + 4, ...), unrolled at compile time.
-template <int L, int W, int T, typename SwT>
+template <int L, int W, int I, typename SwT>
 __device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, const double* lam) {
-  if constexpr (T < K<L>::NTASK) {
-    lam_task<L, L>(T, lane, Z, Y, lam);
-    lam_wave<L, W, T + NT / 64, SwT>(lane, Z, Y, lam);
+  if constexpr (I < LP<L>::plan.n) {
+    constexpr LamTask T = LP<L>::plan.t[I];
+    if constexpr (T.wave == W) {
+      if constexpr (T.kind == 0)
+        row_task<L, T.S, T.k0, T.k1, SwT>(T.chunk, lane, Z, Y, lam);
+      else
+        pair_task<L, SwT>(T.chunk, lane, Z, Y, lam);
+    }
+    lam_wave<L, W, I + 1, SwT>(lane, Z, Y, lam);
   }
 }
 
@@ -340,8 +366,8 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
   // ---- per-item thread constants ----
-  // phase B: thread (rankA, c)
-  const int p2r = tid & 15, p2c = tid >> 4;
+  // phase B: thread (half, rankA, c); half = tid / 128 is wave-uniform
+  const int p2half = tid >> 7, p2r = tid & 15, p2c = (tid >> 4) & 7;
   const int sA_mask = (int)((kOrderANibbles >> (4 * p2r)) & 15u);
   const int sA = __popc(sA_mask);
   const int wb = ((p2c >> 2) * N3 + p2r) * 4 + (p2c & 3);
@@ -362,15 +388,16 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   int u_prev = -1;
 
   const int64_t vbase = I.voff;
-  MobT xr[NC];
+  using RawT = typename std::conditional<IN64, double, float>::type;
+  RawT xraw[NC];   // next tile's raw values (converted when its butterfly starts)
   auto load_tile = [&](int UH) {
     const int64_t base = vbase + ((int64_t)UH << B) + tid;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if constexpr (IN64)
-        xr[c] = mob_from_d<MobT>(vals64[base + (c << 8)]);
+        xraw[c] = vals64[base + (c << 8)];
       else
-        xr[c] = mob_from<MobT>(vals32[base + (c << 8)]);
+        xraw[c] = vals32[base + (c << 8)];
     }
   };
   int UH = torder[I.tofs + W.tb];
@@ -387,6 +414,12 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     }
 
     // ---- Moebius over bits 8-10 in registers, then transpose ----
+    MobT xr[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if constexpr (IN64) xr[c] = mob_from_d<MobT>(xraw[c]);
+      else xr[c] = mob_from<MobT>(xraw[c]);
+    }
 #pragma unroll
     for (int bit = 0; bit < PC; ++bit)
 #pragma unroll
@@ -431,31 +464,67 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       rsweep<PA, 0, 1, 0>(X1, e1);
     }
     __syncthreads();
-    // ---- phase B: thread (sigma_A, c), counters relative to |sigma_A| ----
-    if (tid < NA * NC && sA <= L) {
+    // ---- phase B: thread (half, sigma_A, c), counters relative to |sigma_A|;
+    // the first output site (b bit 3) is split between the two halves of the
+    // workgroup: half 0 walks the sigma = 0 subtree, half 1 the sigma = 1
+    // subtree (which needs only the tau = 1 inputs) ----
+    if (sA <= L) {
       using V = typename Vec4<SwT>::type;
       constexpr int VN = Vec4<SwT>::n;
-      SwT X2[PA + 1][NB];
-#pragma unroll
-      for (int r = 0; r <= PA; ++r) {
-        if (r <= PA - sA) {
-          const V* src = reinterpret_cast<const V*>(S1 + (K<L>::off1v.v[r] + p2r) * R1 + NB * p2c);
-#pragma unroll
-          for (int q = 0; q < NB / VN; ++q) {
-            const V v = src[q];
-            if constexpr (VN == 4) {
-              X2[r][4 * q] = v.x; X2[r][4 * q + 1] = v.y; X2[r][4 * q + 2] = v.z; X2[r][4 * q + 3] = v.w;
-            } else {
-              X2[r][2 * q] = v.x; X2[r][2 * q + 1] = v.y;
-            }
-          }
-        } else {
-#pragma unroll
-          for (int b = 0; b < NB; ++b) X2[r][b] = SwT(0);
-        }
-      }
+      constexpr int H = NB / 2;
       EmitS2<SwT, L> e2{S2 + wb, sA};
-      rsweep<PB, 0, PA + 1, 0>(X2, e2);
+      const SwT* src0 = S1 + p2r * R1 + NB * p2c;
+      if (p2half == 0) {
+        SwT X2[PA + 1][NB];
+#pragma unroll
+        for (int r = 0; r <= PA; ++r) {
+          if (r <= PA - sA) {
+            const V* src = reinterpret_cast<const V*>(src0 + K<L>::off1v.v[r] * R1);
+#pragma unroll
+            for (int q = 0; q < NB / VN; ++q) {
+              const V v = src[q];
+              if constexpr (VN == 4) {
+                X2[r][4 * q] = v.x; X2[r][4 * q + 1] = v.y; X2[r][4 * q + 2] = v.z; X2[r][4 * q + 3] = v.w;
+              } else {
+                X2[r][2 * q] = v.x; X2[r][2 * q + 1] = v.y;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) X2[r][b] = SwT(0);
+          }
+        }
+        SwT Y0[PA + 2][H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          Y0[0][j] = X2[0][j];
+#pragma unroll
+          for (int t = 1; t <= PA; ++t) Y0[t][j] = X2[t][j] + X2[t - 1][H + j];
+          Y0[PA + 1][j] = X2[PA][H + j];
+        }
+        rsweep<PB - 1, 0, PA + 2, 0>(Y0, e2);
+      } else {
+        SwT X1[PA + 1][H];
+#pragma unroll
+        for (int r = 0; r <= PA; ++r) {
+          if (r <= PA - sA) {
+            const V* src = reinterpret_cast<const V*>(src0 + K<L>::off1v.v[r] * R1 + H);
+#pragma unroll
+            for (int q = 0; q < H / VN; ++q) {
+              const V v = src[q];
+              if constexpr (VN == 4) {
+                X1[r][4 * q] = v.x; X1[r][4 * q + 1] = v.y; X1[r][4 * q + 2] = v.z; X1[r][4 * q + 3] = v.w;
+              } else {
+                X1[r][2 * q] = v.x; X1[r][2 * q + 1] = v.y;
+              }
+            }
+          } else {
+#pragma unroll
+            for (int b = 0; b < H; ++b) X1[r][b] = SwT(0);
+          }
+        }
+        rsweep<PB - 1, 1, PA + 1, H>(X1, e2);
+      }
     }
     __syncthreads();
     // ---- phase C: thread per unit sigma_AB, counters relative to |sigma_AB| ----
@@ -495,9 +564,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // ---- final weight core -> Y ----
     switch (wave) {
       case 0: lam_wave<L, 0, 0, SwT>(lane, Z, Y, lamL); break;
-      case 1: lam_wave<L, 1, 1, SwT>(lane, Z, Y, lamL); break;
-      case 2: lam_wave<L, 2, 2, SwT>(lane, Z, Y, lamL); break;
-      default: lam_wave<L, 3, 3, SwT>(lane, Z, Y, lamL); break;
+      case 1: lam_wave<L, 1, 0, SwT>(lane, Z, Y, lamL); break;
+      case 2: lam_wave<L, 2, 0, SwT>(lane, Z, Y, lamL); break;
+      default: lam_wave<L, 3, 0, SwT>(lane, Z, Y, lamL); break;
     }
     __syncthreads();
     // ---- cross-tile sum: E_S += Y[S_L, s_H, |S_H & U_H|] ----
