@@ -170,8 +170,10 @@ struct EmitS1 {
   }
 };
 
-// Phase B -> S2 entries (i, unit of (sigma_A, sigma_B), c): all 9 counters
-// (zeros past the leaf's), for the prefixes with |sigma_A| + |sigma_B| <= L.
+// Phase B -> S2 entries (i, unit of (sigma_A, sigma_B), c) for the leaf's
+// counters i < RC (entries past this unit's range hold zeros), for the
+// prefixes with |sigma_A| + |sigma_B| <= L. Phase C reads only i <= 8 - |sigma_AB|,
+// all written here.
 template <typename SwT, int L>
 struct EmitS2 {
   SwT* S2;   // offset by ((c / 4) * n3 + rankA) * 4 + c % 4
@@ -184,7 +186,7 @@ struct EmitS2 {
         constexpr int UB = K<L>::ub.v[SIG];
         constexpr int N3 = K<L>::N3;
 #pragma unroll
-        for (int i = 0; i <= KAB; ++i) S2[(2 * i * N3 + UB) * 4] = i < RC ? X[i][0] : SwT(0);
+        for (int i = 0; i < RC; ++i) S2[(2 * i * N3 + UB) * 4] = X[i][0];
       }
     }
   }
@@ -534,6 +536,11 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       SwT X3[KAB + 1][NC];
 #pragma unroll
       for (int i = 0; i <= KAB; ++i) {
+        if (i > KAB - sAB) {   // past this unit's counters: zero, not read
+#pragma unroll
+          for (int c = 0; c < NC; ++c) X3[i][c] = SwT(0);
+          continue;
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const V* src = reinterpret_cast<const V*>(S2 + ((2 * i + h) * N3 + u3) * 4);
