@@ -186,7 +186,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       const bool want_fast = opts.kernel != FSI_KERNEL_GENERIC && algo == ALGO_FUSED &&
                              fast_supported(prec) && lh[i] <= kFastMaxL && dh[i] >= fb &&
                              dh[i] - fb <= 12 &&
-                             num_outputs(dh[i], lh[i]) <= (int64_t)kFastKmax * kFastThreads &&
+                             fast_output_slots(dh[i], lh[i]) >= 0 &&
+                             fast_output_slots(dh[i], lh[i]) <= kFastKmax &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
       if (opts.kernel == FSI_KERNEL_REGISTER && !want_fast) {
         free_batch(P);
@@ -256,8 +257,15 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   int64_t fast_tiles = 0;
   for (int i = 0; i < n; ++i)
     if (P->fast_of[P->cls_of[i]] >= 0) fast_tiles += (int64_t)1 << P->classes[P->cls_of[i]].h;
+  // tiles per work item: the largest power of two that still gives every
+  // workgroup slot of the machine at least one item
   int64_t chunk = 1;
-  while (chunk * 2 * n_cu * 2 <= fast_tiles) chunk *= 2;
+  {
+    int slots = n_cu;
+    for (size_t f = 0; f < P->fclasses.size(); ++f)
+      slots = std::max(slots, n_cu * fast_wgs_per_cu(prec, P->fclasses[f].l));
+    while (chunk * 2 * slots <= fast_tiles) chunk *= 2;
+  }
   std::vector<FastItem> fitems;
   int64_t ptot = 0;
   for (int i = 0; i < n; ++i) {
@@ -276,7 +284,14 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min(ntile, tb + cs), 0, ptot});
       ptot += (int64_t)F.nkk * kFastThreads;
     }
-  }  // one launch per order l: items grouped by l (stable, so each group keeps
+  }  std::vector<int2> red_chunks;
+  int n_generic = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!insts[i].fast) { ++n_generic; continue; }
+    const int Mi = P->classes[P->cls_of[i]].M;
+    for (int k0 = 0; k0 < Mi; k0 += 64) red_chunks.push_back(make_int2(i, k0));
+  }
+  // one launch per order l: items grouped by l (stable, so each group keeps
   // the instance order)
   auto item_l = [&](const FastItem& it) { return P->fclasses[P->fast_of[P->cls_of[it.inst]]].l; };
   std::stable_sort(fitems.begin(), fitems.end(),
@@ -355,6 +370,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   }
   const size_t o_fcls = stage(buf, fdev.data(), fdev.size());
   const size_t o_fitems = stage(buf, fitems.data(), fitems.size());
+  const size_t o_red = stage(buf, red_chunks.data(), red_chunks.size());
   const size_t o_torder = stage(buf, torder.data(), torder.size());
   const size_t o_cls = stage(buf, cdev.data(), cdev.size());
   const size_t o_inst = stage(buf, insts.data(), insts.size());
@@ -460,6 +476,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.tile_lds = tile_lds;
   a.mob_lds = mob_lds;
   a.partial = P->partial;
+  a.n_generic = n_generic;
+  a.red_chunks = reinterpret_cast<const int2*>(A + o_red);
+  a.n_red_chunks = (int)red_chunks.size();
+  a.grid_red_chunks = std::max(1, std::min<int>((int)red_chunks.size(), n_cu * 8));
   a.fast = FastLaunch{};
   a.fast.n_items = (int)fitems.size();
   if (!fitems.empty()) {

@@ -95,6 +95,8 @@ double weight_full(int s, int t, int l);
 int64_t sweep_peak_entries(int b, int l);
 // Builds all tables for one class; returns "" or an error message.
 std::string build_class(int d, int l, int b, int algo, ClassHost* out);
+// Output slots per thread the register-phase kernel needs for (d, l), or -1.
+int fast_output_slots(int d, int l);
 // Builds the register-phase kernel tables from an already built fused class
 // with b = 11 and l <= 4 (its final weights and output order).
 std::string build_fast_class(const ClassHost& C, FastClassHost* out);

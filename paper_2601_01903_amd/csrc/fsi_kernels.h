@@ -80,6 +80,9 @@ struct LaunchArgs {
   size_t tile_lds, mob_lds;
   const double* partial;      // register-phase kernel partial sums
   FastLaunch fast;            // n_items == 0: no register-phase stage
+  int n_generic;              // instances of the generic (or two-pass) path
+  const int2* red_chunks;     // (instance, first output) per 64 outputs of fast instances
+  int n_red_chunks, grid_red_chunks;
 };
 
 // Sets the dynamic-LDS limits of the kernels a plan will launch (call once

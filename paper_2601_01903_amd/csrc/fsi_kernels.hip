@@ -190,13 +190,7 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
     }
     const InstDev I = insts[lo];
     const int k = (int)(g - out_offset[lo]);
-    if (I.fast) {
-      const double* P = partial + I.pbase + I.pidx[k];
-      double acc = 0.0;
-      for (int j = 0; j < I.nitems; ++j) acc += P[(int64_t)j * I.pstride];
-      out[I.ooff + k] = (OutT)acc;
-      continue;
-    }
+    if (I.fast) continue;   // written by fast_reduce_kernel
     const ClassDev* C = classes + I.cls;
     const uint32_t oi = C->oinfo[k];
     const uint32_t SH = C->osh[k];
@@ -219,6 +213,35 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
       }
     }
     out[I.ooff + k] = (OutT)acc;
+  }
+}
+
+// Sum of the register-phase kernel's per-item partial results. A workgroup
+// owns 64 outputs of one instance; thread (o, r) adds the items j = r mod 4
+// in increasing order, then the four sums are combined in a fixed order, so
+// the result is bitwise repeatable.
+template <typename OutT>
+__global__ void __launch_bounds__(256)
+fast_reduce_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ chunks,
+                   int n_chunks, const int64_t* __restrict__ out_offset,
+                   const double* __restrict__ partial, OutT* __restrict__ out) {
+  __shared__ double part[4][64];
+  const int o = threadIdx.x & 63, r = threadIdx.x >> 6;
+  for (int ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
+    const int2 c = chunks[ch];
+    const InstDev I = insts[c.x];
+    const int M = (int)(out_offset[c.x + 1] - out_offset[c.x]);
+    const int k = c.y + o;
+    double acc = 0.0;
+    if (k < M) {
+      const double* P = partial + I.pbase + I.pidx[k];
+      for (int j = r; j < I.nitems; j += 4) acc += P[(int64_t)j * I.pstride];
+    }
+    part[r][o] = acc;
+    __syncthreads();
+    if (r == 0 && k < M)
+      out[I.ooff + k] = (OutT)(((part[0][o] + part[1][o]) + part[2][o]) + part[3][o]);
+    __syncthreads();
   }
 }
 
@@ -342,9 +365,12 @@ hipError_t configure_kernels(int prec, int algo, size_t tile_lds, size_t mob_lds
 }
 
 int num_stages(const LaunchArgs& a) {
-  // fused: [register-phase kernel], [generic tile kernel], reduce
+  // fused: [register-phase kernel per order l], [generic tile kernel],
+  //        [generic reduce], [register-phase reduce]
   // two-pass: Moebius low pass, high passes, tile, reduce
-  if (a.algo == ALGO_FUSED) return fast_groups(a.fast, nullptr) + (a.n_tile_items > 0) + 1;
+  if (a.algo == ALGO_FUSED)
+    return fast_groups(a.fast, nullptr) + (a.n_tile_items > 0) + (a.n_generic > 0) +
+           (a.n_red_chunks > 0);
   return 3 + a.n_mob_passes;
 }
 
@@ -352,7 +378,14 @@ template <typename InT, typename MobT, typename SwT>
 hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   const int last = num_stages(a) - 1;
   if (stage < 0 || stage > last) return hipErrorInvalidValue;
-  if (stage == last) {
+  if (a.algo == ALGO_FUSED && a.n_red_chunks > 0 && stage == last) {
+    hipLaunchKernelGGL(fast_reduce_kernel<InT>, dim3(a.grid_red_chunks), dim3(256), 0, st,
+                       a.insts, a.red_chunks, a.n_red_chunks, a.out_offset, a.partial,
+                       static_cast<InT*>(a.out));
+    return hipGetLastError();
+  }
+  if (a.algo != ALGO_FUSED ? stage == last
+                           : (a.n_generic > 0 && stage == last - (a.n_red_chunks > 0))) {
     hipLaunchKernelGGL(reduce_kernel<InT>, dim3(a.grid_reduce), dim3(256), 0, st, a.classes,
                        a.insts, a.n_inst, a.out_offset, a.total_out, a.Y, a.partial,
                        static_cast<InT*>(a.out));

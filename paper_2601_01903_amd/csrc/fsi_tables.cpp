@@ -223,6 +223,18 @@ std::string build_class(int d, int l, int b, int algo, ClassHost* C) {
   return "";
 }
 
+int fast_output_slots(int d, int l) {
+  if (d < t11::B || l > 4 || l > d) return -1;
+  const int h = d - t11::B;
+  int slots = 0;
+  for (int sL = 0; sL <= l; ++sL) {
+    int64_t n = 0;
+    for (int sH = 0; sH <= std::min(l - sL, h); ++sH) n += binom(t11::B, sL) * binom(h, sH);
+    slots += (int)((n + kFastThreads - 1) / kFastThreads);
+  }
+  return slots;
+}
+
 std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
   using namespace t11;
   const int l = C.l, b = C.b, h = C.h;

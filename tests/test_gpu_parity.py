@@ -135,6 +135,62 @@ def test_register_kernel_fp64_exact(d, l, kernel):
     assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=8)) < 1e-12
 
 
+@pytest.mark.parametrize("d,l", [(21, 3), (22, 2), (23, 1), (22, 3), (21, 4)])
+def test_register_kernel_wide_high_part(d, l):
+    """Up to 12 high bits (2^12 tiles per instance); d = 21, l = 4 needs more
+    output slots than the register-phase kernel holds and takes the generic
+    kernel (the plan must still succeed)."""
+    say(f"[case] wide high part d={d} l={l}")
+    v = np.random.default_rng(5000 + d * 7 + l).integers(-3, 4, size=1 << d).astype(np.float64)
+    got, info = gpu_apply(v, d, l)
+    say(f"  tile_bits={info['tile_bits']}")
+    assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=16)) < 1e-12
+
+
+def _ragged_batch():
+    ds, ls = games.ragged_specs(512)
+    built = games.build_many(lambda i: games.ragged_instance(i, ds[i]), range(len(ds)), threads=16)
+    return ds, ls, [v for _, v in built]
+
+
+@pytest.mark.parametrize("prec", ["f32_compensated", "f32"])
+def test_ragged_batch_512_fp32(prec):
+    """The 512-instance ragged batch (d ~ U{8..20}, l ~ U{1..4}, tree games),
+    FP32 storage, one graph replay, every instance against the oracle on the
+    same FP32 values: <= 1e-6 normwise."""
+    fsi = fsi_mod()
+    ds, ls, vals = _ragged_batch()
+    say(f"[case] ragged batch n={len(ds)} {prec}, {sum(1 << d for d in ds)} values")
+    v32 = [v.astype(np.float32) for v in vals]
+    bp = fsi.BatchPlan(ds, ls, dtype="f32", precision=prec)
+    flat = torch.from_numpy(np.concatenate(v32)).to(DEV)
+    out = bp.apply(flat, graph=True)
+    torch.cuda.synchronize()
+    o = out.double().cpu().numpy()
+    worst = 0.0
+    for i, (v, d, l) in enumerate(zip(v32, ds, ls)):
+        ref = oracle.fsi_c(v.astype(np.float64), d, l, nthreads=16)
+        err = normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], ref)
+        worst = max(worst, err)
+        assert err < 1e-6, (i, d, l, err)
+    say(f"  worst normwise err {worst:.3e}")
+    bp.close()
+
+
+def test_ragged_batch_512_fp64():
+    fsi = fsi_mod()
+    ds, ls, vals = _ragged_batch()
+    say(f"[case] ragged batch n={len(ds)} FP64")
+    bp = fsi.BatchPlan(ds, ls, dtype="f64")
+    out = bp.apply(torch.from_numpy(np.concatenate(vals)).to(DEV), graph=True)
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
+        ref = oracle.fsi_c(v, d, l, nthreads=16)
+        assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], ref) < 1e-12, (i, d, l)
+    bp.close()
+
+
 @pytest.mark.parametrize("d,l,tb", [(1, 1, 0), (2, 2, 0), (5, 5, 0), (9, 9, 0), (12, 4, 0),
                                     (13, 4, 0), (10, 3, 3), (11, 1, 4), (16, 2, 0),
                                     (15, 4, 7), (17, 3, 0)])
