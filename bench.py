@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--check-sample", type=int, default=4)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the heuristic schedule instead of timing candidates at plan time")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -110,8 +112,11 @@ def main():
     log(f"generated {n} instances in {time.time() - t0:.1f}s")
 
     x32 = torch.from_numpy(vals32).to(dev)
+    t0 = time.time()
     bp32 = BatchPlan([d] * n, [l] * n, dtype="f32", precision=args.precision, algo=args.algo,
-                     tile_bits=args.tile_bits)
+                     tile_bits=args.tile_bits, autotune=not args.no_autotune)
+    sched = bp32.schedule()
+    log(f"plan in {time.time() - t0:.2f}s, schedule {sched}")
     M = bp32.out_offset[1]
     out32 = torch.empty(bp32.out_offset[-1], dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
@@ -269,6 +274,7 @@ def main():
                      "kernel": f"stage {dom} of {ns}", "kernel_ms": stage_ms[dom]},
         "stage_ms": stage_ms,
         "graph_replay_ms_per_step": graph_ms,
+        "schedule": sched,
         "hbm_frac_whole_step": (alg_bytes + n * M * 4) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "fp64": fp64,
         "speedup_vs_plain_fp64": (fp64["plain_ms_per_pass"] / ms_per_step) if fp64 else None,

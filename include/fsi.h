@@ -86,15 +86,17 @@ typedef struct {
   int32_t algo;                  /* fsi_algo, default FSI_ALGO_AUTO          */
   int32_t tile_bits;             /* b, 0 = choose (autotuned if enabled)     */
   int32_t block_threads;         /* workgroup size, 0 = choose               */
-  int32_t autotune;              /* 1 = time candidate schedules at plan time*/
+  int32_t autotune;              /* 1 = time candidate schedules at plan     */
+                                 /* time (see fsi_schedule), keep the best   */
   int32_t kernel;                /* fsi_kernel, default FSI_KERNEL_AUTO      */
   int32_t reserved[3];           /* must be 0                                */
 } fsi_plan_opts;
 
-/* Tile kernel of the fused algorithm. The register-phase kernel covers
- * FP32 storage (F32, F32_COMPENSATED, F32_FP64MOB) at d >= 12 and FP64 at
- * d >= 11, with l <= 4 and d <= 24; the generic LDS kernel covers every
- * (d, l). AUTO picks the register-phase kernel where it applies. */
+/* Tile kernel of the fused algorithm. The register-phase kernel (tiles of
+ * 11 low bits) covers every storage dtype and precision except
+ * F32_FP64REG, at 11 <= d <= 23 and l <= 4 while its output slots suffice
+ * (all such (d, l) except d >= 21 with l = 4); the generic LDS kernel covers
+ * every (d, l). AUTO picks the register-phase kernel where it applies. */
 typedef enum {
   FSI_KERNEL_AUTO = 0,
   FSI_KERNEL_GENERIC = 1,
@@ -103,6 +105,26 @@ typedef enum {
 
 typedef struct fsi_plan_s* fsi_plan_t;
 typedef struct fsi_batch_plan_s* fsi_batch_plan_t;
+
+/* The schedule a plan runs (fsi_plan_schedule / fsi_batch_schedule).
+ * With fsi_plan_opts.autotune = 1, plan creation builds the plan for each
+ * candidate schedule, times one apply of each on zero-filled scratch
+ * buffers of the plan's size (allocated and freed inside the call) on a
+ * private stream, and keeps the fastest. Candidates: for the fused
+ * algorithm the register-phase kernel at 1/2x, 1x, 2x and 4x the default
+ * tiles per work item and the generic kernel at the largest tile that fits
+ * LDS and 1 or 2 bits less; for the two-pass algorithm 4, 5 or 6 bits per
+ * strided high Moebius pass, with the largest tile or 1 bit less. The
+ * choice is cached per (dtype, precision, algo, kernel, tile_bits, multiset
+ * of (d, l)) for the life of the process. */
+typedef struct {
+  int32_t autotuned;        /* 1 if chosen by timing                         */
+  int32_t fast_instances;   /* instances on the register-phase kernel       */
+  int32_t tiles_per_item;   /* register-phase kernel: tiles per work item   */
+  int32_t tile_shift;       /* generic tile: bits below the largest fitting */
+  int32_t mob_group;        /* two-pass: bits per strided high pass, else 0 */
+  float tuned_ms;           /* measured time of the chosen schedule (ms)    */
+} fsi_schedule;
 
 /* Fill opts with the defaults listed above. */
 fsi_status fsi_default_opts(fsi_plan_opts* opts);
@@ -182,6 +204,10 @@ fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev
                                    void* out_dev, int stage, hipStream_t stream);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
+/* Schedule of a plan (host struct filled by the call). */
+fsi_status fsi_plan_schedule(fsi_plan_t plan, fsi_schedule* out);
+fsi_status fsi_batch_schedule(fsi_batch_plan_t plan, fsi_schedule* out);
+
 const char* fsi_last_error(void);
 
 #ifdef __cplusplus

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -73,6 +74,7 @@ struct fsi_batch_plan_s {
   std::vector<int> fast_of;        // per class: index into fclasses or -1
   LaunchArgs args{};
   int tile_bits_reported = 0;
+  fsi_schedule sched{};            // the schedule this plan was built with
   // graph cache
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -127,8 +129,16 @@ size_t stage(std::vector<unsigned char>& buf, const T* data, size_t count) {
   return off;
 }
 
+// Schedule knobs the autotuner varies (the defaults are the heuristics).
+struct Sched {
+  int kernel = -1;      // fsi_kernel to use, -1: the option's
+  int tb_shift = 0;     // generic tile: bits relative to the largest that fits LDS (<= 0)
+  int chunk_shift = 0;  // register-phase kernel: log2 tiles per item relative to the default
+  int mob_group = 0;    // two-pass: bits per strided high Moebius pass (0: 6)
+};
+
 fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts* opts_in,
-                       bool single, fsi_batch_plan_s** out) {
+                       bool single, fsi_batch_plan_s** out, const Sched& sc = Sched{}) {
   *out = nullptr;
   if (n < 1) return fail(FSI_ERR_INVALID_ARG, "n must be >= 1");
   if (!dh || !lh) return fail(FSI_ERR_INVALID_ARG, "null d or l array");
@@ -183,18 +193,20 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       // register-phase kernel: fused algorithm, l <= 4, tile of 11 bits,
       // at most 12 high bits, at most 25 outputs per thread
       const int fb = kFastTileBits;
-      const bool want_fast = opts.kernel != FSI_KERNEL_GENERIC && algo == ALGO_FUSED &&
+      const int kern = sc.kernel >= 0 ? sc.kernel : opts.kernel;
+      const bool want_fast = kern != FSI_KERNEL_GENERIC && algo == ALGO_FUSED &&
                              fast_supported(prec) && lh[i] <= kFastMaxL && dh[i] >= fb &&
                              dh[i] - fb <= 12 &&
                              fast_output_slots(dh[i], lh[i]) >= 0 &&
                              fast_output_slots(dh[i], lh[i]) <= kFastKmax &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
-      if (opts.kernel == FSI_KERNEL_REGISTER && !want_fast) {
+      if (kern == FSI_KERNEL_REGISTER && !want_fast) {
         free_batch(P);
         return fail(FSI_ERR_UNSUPPORTED, "register-phase kernel does not apply to instance " +
                                              std::to_string(i));
       }
-      const int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
+      int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
+      if (!want_fast && opts.tile_bits == 0) b = std::max(1, b + sc.tb_shift);
       std::string err = build_class(dh[i], lh[i], b, algo, &C);
       if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
       const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
@@ -265,6 +277,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     for (size_t f = 0; f < P->fclasses.size(); ++f)
       slots = std::max(slots, n_cu * fast_wgs_per_cu(prec, P->fclasses[f].l));
     while (chunk * 2 * slots <= fast_tiles) chunk *= 2;
+    if (sc.chunk_shift > 0) chunk <<= sc.chunk_shift;
+    if (sc.chunk_shift < 0) chunk = std::max<int64_t>(1, chunk >> -sc.chunk_shift);
   }
   std::vector<FastItem> fitems;
   int64_t ptot = 0;
@@ -329,7 +343,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     const ClassHost& C = P->classes[P->cls_of[i]];
     int lo = C.b, p = 0;
     while (lo < dh[i]) {
-      const int G = std::min(6, dh[i] - lo);
+      const int G = std::min(sc.mob_group > 0 ? sc.mob_group : 6, dh[i] - lo);
       const int cb = std::min(lo, kMaxTileBits - G);
       if (p >= kMaxMobPasses) { free_batch(P); return fail(FSI_ERR_INTERNAL, "too many passes"); }
       const int64_t nblk = (int64_t)1 << (dh[i] - G - cb);
@@ -498,7 +512,146 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       a.fast.grid[l] = nl > 0 ? std::max(1, std::min(nl, n_cu * fast_wgs_per_cu(prec, l))) : 0;
     }
   }
+  P->sched.autotuned = 0;
+  P->sched.fast_instances = 0;
+  for (int i = 0; i < n; ++i) P->sched.fast_instances += insts[i].fast;
+  P->sched.tiles_per_item = fitems.empty() ? 0 : (int)chunk;
+  P->sched.tile_shift = sc.tb_shift;
+  P->sched.mob_group = algo == ALGO_TWO_PASS ? (sc.mob_group > 0 ? sc.mob_group : 6) : 0;
+  P->sched.tuned_ms = 0.f;
   *out = P;
+  return FSI_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// With fsi_plan_opts.autotune = 1 the plan is built for each candidate
+// schedule, each candidate is timed on zero-filled device buffers of the
+// plan's size (the kernels' work does not depend on the values), and the
+// fastest is kept. Results are cached per (dtype, precision, algo, kernel,
+// tile_bits, multiset of (d, l)) for the life of the process.
+std::mutex g_tune_mu;
+std::map<std::string, Sched>& tune_cache() {
+  static std::map<std::string, Sched> m;
+  return m;
+}
+
+std::string tune_key(int n, const int* dh, const int* lh, const fsi_plan_opts& o) {
+  std::map<std::pair<int, int>, int> cnt;
+  for (int i = 0; i < n; ++i) ++cnt[{dh[i], lh[i]}];
+  std::string k = std::to_string(o.dtype) + "/" + std::to_string(o.precision) + "/" +
+                  std::to_string(o.algo) + "/" + std::to_string(o.kernel) + "/" +
+                  std::to_string(o.tile_bits);
+  for (auto& e : cnt)
+    k += ";" + std::to_string(e.first.first) + "," + std::to_string(e.first.second) + "x" +
+         std::to_string(e.second);
+  return k;
+}
+
+// Median device time of launch_apply over a few runs, in ms (< 0 on error).
+float time_plan(fsi_batch_plan_s* P, void* vin, void* vout, hipStream_t st) {
+  LaunchArgs a = P->args;
+  a.values = vin;
+  a.out = vout;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.f; }
+  std::vector<float> t;
+  bool ok = true;
+  for (int r = 0; r < 7 && ok; ++r) {
+    ok = hipEventRecord(e0, st) == hipSuccess && launch_apply(a, st) == hipSuccess &&
+         hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float ms = 0.f;
+    if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && r >= 2) t.push_back(ms);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok || t.empty()) return -1.f;
+  std::sort(t.begin(), t.end());
+  return t[t.size() / 2];
+}
+
+fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts* opts_in,
+                       bool single, fsi_batch_plan_s** out) {
+  fsi_plan_opts opts;
+  fsi_default_opts(&opts);
+  if (opts_in) opts = *opts_in;
+  if (!opts.autotune) return build_batch(n, dh, lh, opts_in, single, out);
+  if (n < 1 || !dh || !lh) return build_batch(n, dh, lh, opts_in, single, out);
+  const std::string key = tune_key(n, dh, lh, opts);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+      fsi_status st = build_batch(n, dh, lh, opts_in, single, out, it->second);
+      if (st == FSI_OK) (*out)->sched.autotuned = 1;
+      return st;
+    }
+  }
+  // candidates
+  std::vector<Sched> cand;
+  const bool fused = opts.algo != FSI_ALGO_TWO_PASS;
+  if (fused) {
+    if (opts.kernel != FSI_KERNEL_GENERIC)
+      for (int cs = -1; cs <= 2; ++cs) { Sched s; s.kernel = opts.kernel; s.chunk_shift = cs; cand.push_back(s); }
+    if (opts.kernel != FSI_KERNEL_REGISTER)
+      for (int tb = 0; tb >= (opts.tile_bits ? 0 : -2); --tb) {
+        Sched s; s.kernel = FSI_KERNEL_GENERIC; s.tb_shift = tb; cand.push_back(s);
+      }
+  } else {
+    for (int g = 4; g <= 6; ++g)
+      for (int tb = 0; tb >= (opts.tile_bits ? 0 : -1); --tb) {
+        Sched s; s.mob_group = g; s.tb_shift = tb; cand.push_back(s);
+      }
+  }
+  fsi_batch_plan_s* best = nullptr;
+  float best_ms = 0.f;
+  Sched best_s;
+  fsi_status first_err = FSI_OK;
+  std::string first_msg;
+  void* vin = nullptr;
+  void* vout = nullptr;
+  hipStream_t st = nullptr;
+  for (const Sched& sc : cand) {
+    fsi_batch_plan_s* P = nullptr;
+    fsi_status s = build_batch(n, dh, lh, opts_in, single, &P, sc);
+    if (s != FSI_OK) {
+      if (first_err == FSI_OK) { first_err = s; first_msg = g_err; }
+      continue;
+    }
+    if (!st) {
+      const size_t elem = opts.dtype == FSI_DTYPE_F64 ? 8 : 4;
+      const size_t nin = (size_t)P->voff[n] * elem, nout = (size_t)P->ooff[n] * elem;
+      if (hipMalloc(&vin, nin) != hipSuccess || hipMalloc(&vout, nout) != hipSuccess ||
+          hipMemset(vin, 0, nin) != hipSuccess ||
+          hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        free_batch(P);
+        if (vin) (void)hipFree(vin);
+        if (vout) (void)hipFree(vout);
+        return fail(FSI_ERR_OUT_OF_MEMORY, "autotune: scratch buffers");
+      }
+    }
+    const float ms = time_plan(P, vin, vout, st);
+    if (ms >= 0.f && (!best || ms < best_ms)) {
+      if (best) free_batch(best);
+      best = P; best_ms = ms; best_s = sc;
+    } else {
+      free_batch(P);
+    }
+  }
+  if (st) (void)hipStreamDestroy(st);
+  if (vin) (void)hipFree(vin);
+  if (vout) (void)hipFree(vout);
+  if (!best) {
+    if (first_err != FSI_OK) { g_err = first_msg; return first_err; }
+    return fail(FSI_ERR_INTERNAL, "autotune: no candidate could be timed");
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache()[key] = best_s;
+  }
+  best->sched.autotuned = 1;
+  best->sched.tuned_ms = best_ms;
+  *out = best;
   return FSI_OK;
 }
 
@@ -525,7 +678,7 @@ fsi_status fsi_plan_ex(int d, int l, const fsi_plan_opts* opts, fsi_plan_t* out)
   if (!(1 <= d && d <= kMaxD && 1 <= l && l <= d))
     return fail(FSI_ERR_INVALID_ARG, "need 1 <= l <= d <= 30");
   fsi_batch_plan_s* bp = nullptr;
-  fsi_status st = build_batch(1, &d, &l, opts, true, &bp);
+  fsi_status st = build_tuned(1, &d, &l, opts, true, &bp);
   if (st != FSI_OK) return st;
   auto* p = new (std::nothrow) fsi_plan_s();
   if (!p) { free_batch(bp); return fail(FSI_ERR_OUT_OF_MEMORY, "host allocation failed"); }
@@ -593,7 +746,7 @@ fsi_status fsi_plan_batched(int n, const int* d_host, const int* l_host,
   if (!out) return fail(FSI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   fsi_batch_plan_s* bp = nullptr;
-  fsi_status st = build_batch(n, d_host, l_host, opts, false, &bp);
+  fsi_status st = build_tuned(n, d_host, l_host, opts, false, &bp);
   if (st != FSI_OK) return st;
   *out = bp;
   return FSI_OK;
@@ -672,6 +825,18 @@ fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev
   a.values = values_dev;
   a.out = out_dev;
   HIP_TRY(launch_stage(a, stage, stream));
+  return FSI_OK;
+}
+
+fsi_status fsi_batch_schedule(fsi_batch_plan_t plan, fsi_schedule* out) {
+  if (!plan || !out) return fail(FSI_ERR_INVALID_ARG, "null plan or output");
+  *out = plan->sched;
+  return FSI_OK;
+}
+
+fsi_status fsi_plan_schedule(fsi_plan_t plan, fsi_schedule* out) {
+  if (!plan || !out) return fail(FSI_ERR_INVALID_ARG, "null plan or output");
+  *out = plan->bp->sched;
   return FSI_OK;
 }
 

@@ -29,7 +29,8 @@ EXPORTS = ["fsi_default_opts", "fsi_num_outputs", "fsi_plan", "fsi_plan_ex",
            "fsi_plan_destroy", "fsi_output_masks", "fsi_plan_info", "fsi_apply",
            "fsi_mobius", "fsi_plan_batched", "fsi_batch_plan_destroy",
            "fsi_batch_offsets", "fsi_apply_batched", "fsi_apply_batched_nograph",
-           "fsi_batch_num_stages", "fsi_apply_batched_stage", "fsi_last_error"]
+           "fsi_batch_num_stages", "fsi_apply_batched_stage", "fsi_plan_schedule",
+           "fsi_batch_schedule", "fsi_last_error"]
 
 
 class FsiError(RuntimeError):
@@ -43,6 +44,16 @@ class Opts(ctypes.Structure):
                 ("algo", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("autotuned", ctypes.c_int32), ("fast_instances", ctypes.c_int32),
+                ("tiles_per_item", ctypes.c_int32), ("tile_shift", ctypes.c_int32),
+                ("mob_group", ctypes.c_int32), ("tuned_ms", ctypes.c_float)]
+
+
+def _sched_dict(s: Schedule) -> dict:
+    return {k: getattr(s, k) for k, _ in Schedule._fields_}
 
 
 _lib = None
@@ -77,6 +88,8 @@ def load() -> ctypes.CDLL:
     lib.fsi_apply_batched_nograph.argtypes = [vp, vp, vp, vp]
     lib.fsi_batch_num_stages.argtypes = [vp]
     lib.fsi_apply_batched_stage.argtypes = [vp, vp, vp, i32, vp]
+    lib.fsi_plan_schedule.argtypes = [vp, P(Schedule)]
+    lib.fsi_batch_schedule.argtypes = [vp, P(Schedule)]
     lib.fsi_last_error.argtypes = []
     lib.fsi_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -98,7 +111,7 @@ def num_outputs(d: int, l: int) -> int:
 
 
 def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
-              block_threads=0, kernel="auto") -> Opts:
+              block_threads=0, kernel="auto", autotune=False) -> Opts:
     o = Opts()
     _check(load().fsi_default_opts(ctypes.byref(o)), "fsi_default_opts")
     o.dtype = DTYPES[dtype]
@@ -107,6 +120,7 @@ def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
     o.tile_bits = int(tile_bits)
     o.block_threads = int(block_threads)
     o.kernel = KERNELS[kernel]
+    o.autotune = 1 if autotune else 0
     return o
 
 
@@ -133,11 +147,11 @@ class Plan:
 
     def __init__(self, d: int, l: int, dtype: str = "f64", precision: str = "auto",
                  algo: str = "auto", tile_bits: int = 0, block_threads: int = 0,
-                 kernel: str = "auto"):
+                 kernel: str = "auto", autotune: bool = False):
         lib = load()
         self.d, self.l, self.dtype = d, l, dtype
         self._h = ctypes.c_void_p()
-        opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel)
+        opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel, autotune)
         _check(lib.fsi_plan_ex(d, l, ctypes.byref(opts), ctypes.byref(self._h)), "fsi_plan_ex")
         self.M = num_outputs(d, l)
 
@@ -158,6 +172,11 @@ class Plan:
                                     ctypes.byref(al), ctypes.byref(pr)), "fsi_plan_info")
         return {"tile_bits": tb.value, "block_threads": bt.value, "algo": al.value,
                 "precision": pr.value}
+
+    def schedule(self) -> dict:
+        sc = Schedule()
+        _check(load().fsi_plan_schedule(self._h, ctypes.byref(sc)), "fsi_plan_schedule")
+        return _sched_dict(sc)
 
     def output_masks(self):
         import numpy as np
@@ -190,7 +209,7 @@ class BatchPlan:
 
     def __init__(self, ds: Sequence[int], ls: Sequence[int], dtype: str = "f32",
                  precision: str = "auto", algo: str = "auto", tile_bits: int = 0,
-                 block_threads: int = 0, kernel: str = "auto"):
+                 block_threads: int = 0, kernel: str = "auto", autotune: bool = False):
         lib = load()
         n = len(ds)
         if len(ls) != n:
@@ -199,7 +218,7 @@ class BatchPlan:
         self.ds, self.ls = list(ds), list(ls)
         darr = (ctypes.c_int * n)(*ds)
         larr = (ctypes.c_int * n)(*ls)
-        opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel)
+        opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel, autotune)
         self._h = ctypes.c_void_p()
         _check(lib.fsi_plan_batched(n, darr, larr, ctypes.byref(opts), ctypes.byref(self._h)),
                "fsi_plan_batched")
@@ -231,6 +250,11 @@ class BatchPlan:
         _check(fn(self._h, ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                   _stream_handle(stream)), "fsi_apply_batched")
         return out
+
+    def schedule(self) -> dict:
+        sc = Schedule()
+        _check(load().fsi_batch_schedule(self._h, ctypes.byref(sc)), "fsi_batch_schedule")
+        return _sched_dict(sc)
 
     def num_stages(self) -> int:
         return int(load().fsi_batch_num_stages(self._h))

@@ -332,3 +332,38 @@ def test_error_paths_on_device():
     p.close()
     with pytest.raises(fsi.FsiError):
         fsi.BatchPlan([4, 3], [5, 1])
+
+
+def test_autotuned_plans_match_oracle():
+    """fsi_plan_opts.autotune: candidates are timed at plan time, the chosen
+    schedule is reported, cached per shape, and the results stay exact."""
+    fsi = fsi_mod()
+    say("[case] autotune single d=16 l=3 f32")
+    g = games.tree_game(16, 60, 5, games.rng_for(96, 1))
+    v32 = games.tree_values(g).astype(np.float32)
+    p = fsi.Plan(16, 3, dtype="f32", precision="f32_compensated", autotune=True)
+    sc = p.schedule()
+    say(f"  schedule {sc}")
+    assert sc["autotuned"] == 1 and sc["tuned_ms"] > 0
+    got = p.apply(torch.from_numpy(v32).to(DEV)).double().cpu().numpy()
+    assert normwise(got, oracle.fsi_c(v32.astype(np.float64), 16, 3, nthreads=8)) < 1e-6
+    p2 = fsi.Plan(16, 3, dtype="f32", precision="f32_compensated", autotune=True)
+    assert p2.schedule()["autotuned"] == 1          # from the cache
+    p.close()
+    p2.close()
+    say("[case] autotune batched ragged FP64, fused and two-pass")
+    ds, ls = [9, 12, 14, 11, 13], [2, 4, 3, 1, 4]
+    vals = _batch_inputs(ds, 8000)
+    flat = torch.from_numpy(np.concatenate(vals)).to(DEV)
+    for algo in ("fused", "two_pass"):
+        bp = fsi.BatchPlan(ds, ls, dtype="f64", algo=algo, autotune=True)
+        sc = bp.schedule()
+        say(f"  {algo}: {sc}")
+        assert sc["autotuned"] == 1
+        if algo == "two_pass":
+            assert sc["mob_group"] in (4, 5, 6)
+        o = bp.apply(flat, graph=True).cpu().numpy()
+        for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
+            assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]],
+                            oracle.fsi_exact_int(v, d, l, nthreads=8)) < INT_TOL[algo], (algo, i)
+        bp.close()
