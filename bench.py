@@ -51,7 +51,7 @@ def measured_traffic(workload_key: str):
     """HBM bytes per launch of the tile kernel from the committed counter summary
     (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration), or None when
     that summary was taken on other kernel sources or another workload."""
-    path = os.path.join(ROOT, "profiles", "fsi_fast_tile_d20_l4_x256_hbm_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "tile11_kernel_d20_l4_x256_hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
