@@ -12,6 +12,11 @@ import subprocess
 import numpy as np
 
 from .fsi_oracle import (  # noqa: F401
+    INDICES,
+    bernoulli_exact,
+    index_weight_exact,
+    index_weight_table_f64,
+    interaction,
     fsi,
     fsi_batch,
     mobius,
@@ -60,15 +65,17 @@ def _load():
     return _lib
 
 
-def fsi_c(v, d: int, l: int, nthreads: int = 1) -> np.ndarray:
-    """Same result as ``fsi`` (same algorithm), computed by the C twin."""
+def fsi_c(v, d: int, l: int, nthreads: int = 1, index: str = "fsi") -> np.ndarray:
+    """Same result as ``fsi`` (or ``interaction`` for another index; same
+    algorithm), computed by the C twin."""
     if not (1 <= l <= d):
         raise ValueError("need 1 <= l <= d")
     lib = _load()
     v = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
     if v.size != 1 << d:
         raise ValueError("v must have 2^d entries")
-    W = np.ascontiguousarray(weight_table_f64(d, l))
+    W = np.ascontiguousarray(weight_table_f64(d, l) if index == "fsi"
+                             else index_weight_table_f64(index, d, l))
     masks = np.ascontiguousarray(output_masks(d, l).astype(np.int64))
     E = np.empty(masks.size, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)

@@ -48,6 +48,11 @@ __all__ = [
     "superset_masks",
     "fsi",
     "fsi_batch",
+    "INDICES",
+    "bernoulli_exact",
+    "index_weight_exact",
+    "index_weight_table_f64",
+    "interaction",
 ]
 
 
@@ -158,11 +163,16 @@ def fsi(v: np.ndarray, d: int, l: int) -> np.ndarray:
     """
     if not (1 <= l <= d):
         raise ValueError("need 1 <= l <= d")
+    return _superset_weighted(v, d, l, weight_table_f64(d, l))
+
+
+def _superset_weighted(v, d: int, l: int, W: np.ndarray) -> np.ndarray:
+    """E_S = sum over supersets T of S of W[|S|, |T|] * a(T), a = Moebius(v),
+    for every |S| <= l in canonical order (brute force over (S, T) pairs)."""
     v = np.asarray(v, dtype=np.float64)
     if v.size != 1 << d:
         raise ValueError("v must have 2^d entries")
     a = mobius(v)
-    W = weight_table_f64(d, l)
     out_masks = output_masks(d, l)
     out = np.empty(out_masks.size, dtype=np.float64)
     pc_cache = _popcount(np.arange(1 << d, dtype=np.int64))
@@ -178,3 +188,84 @@ def fsi(v: np.ndarray, d: int, l: int) -> np.ndarray:
 def fsi_batch(values, ds, ls):
     """Per-instance ``fsi`` over a list of value vectors."""
     return [fsi(v, d, l) for v, d, l in zip(values, ds, ls)]
+
+
+# ---------------------------------------------------------------------------
+# Other cardinal interaction indices (Appendix A: SII, k-SII, STII, BII).
+#
+# Each is linear in v and, written on the Moebius transform, gives every
+# superset T of S a weight that depends only on s = |S| and t = |T|:
+#     I_S = sum_{T superset of S} W_index(s, t) * a(T),   |S| <= l,
+# which is the same shape as FSI's closed form, so the same superset sums
+# compute them. The Moebius-side weights used here:
+#   sii   1 / (t - s + 1)                (SII's discrete-derivative weights
+#                                         of Appendix A, summed over supersets)
+#   bii   2^-(t - s)                      (uniform weights over the complement)
+#   stii  [t == s] for s < l;  1 / C(t, l) for s == l
+#         (top order receives every higher Moebius coefficient split evenly
+#          over its l-subsets; lower orders are the Moebius coefficients)
+#   ksii  [t == 0] for s == 0; for s >= 1
+#         sum_{j=0}^{min(l-s, t-s)} B_j C(t-s, j) / (t-s-j+1)
+#         with the Bernoulli numbers B_j (B_1 = -1/2): the SII of S plus the
+#         Bernoulli-weighted SII of its supersets up to order l
+#   fsi   the weights of Eq. 3, 4 and 7 (``weight_table_f64``)
+# For S = empty, FSI, STII and k-SII give v(empty) (a Moebius coefficient);
+# SII and BII follow their own definitions (Delta_empty v(T) = v(T)).
+# ---------------------------------------------------------------------------
+
+INDICES = ("fsi", "stii", "sii", "ksii", "bii")
+
+
+def bernoulli_exact(n: int):
+    """Bernoulli numbers B_0 .. B_n as Fractions from the recurrence
+    sum_{j=0}^{m} C(m+1, j) B_j = 0 for m >= 1, B_0 = 1 (so B_1 = -1/2)."""
+    B = [Fraction(0)] * (n + 1)
+    B[0] = Fraction(1)
+    for m in range(1, n + 1):
+        B[m] = -sum(comb(m + 1, j) * B[j] for j in range(m)) / (m + 1)
+    return B
+
+
+def index_weight_exact(index: str, s: int, t: int, l: int) -> Fraction:
+    """Exact Moebius-side weight W_index(s, t) for |S| = s <= l, |T| = t >= s."""
+    if not (0 <= s <= l) or t < s:
+        raise ValueError("need 0 <= s <= l and t >= s")
+    if index == "fsi":
+        if t == s:
+            return Fraction(1)
+        return weight_exact(s, t, l) if (t > l and s >= 1) else Fraction(0)
+    if index == "sii":
+        return Fraction(1, t - s + 1)
+    if index == "bii":
+        return Fraction(1, 1 << (t - s))
+    if index == "stii":
+        if s < l:
+            return Fraction(1 if t == s else 0)
+        return Fraction(1, comb(t, l))
+    if index == "ksii":
+        if s == 0:
+            return Fraction(1 if t == 0 else 0)
+        B = bernoulli_exact(l)
+        n = t - s
+        return sum((B[j] * comb(n, j) / (n - j + 1) for j in range(0, min(l - s, n) + 1)),
+                   Fraction(0))
+    raise ValueError("unknown index %r (one of %s)" % (index, ", ".join(INDICES)))
+
+
+def index_weight_table_f64(index: str, d: int, l: int) -> np.ndarray:
+    """W[s, t] (shape (l+1, d+1)) of ``index_weight_exact``, each entry an
+    exact rational rounded once to FP64; zero for t < s."""
+    W = np.zeros((l + 1, d + 1), dtype=np.float64)
+    for s in range(0, l + 1):
+        for t in range(s, d + 1):
+            W[s, t] = float(index_weight_exact(index, s, t, l))
+    return W
+
+
+def interaction(v: np.ndarray, d: int, l: int, index: str = "fsi") -> np.ndarray:
+    """Scores I_S of the given index for all |S| <= l (canonical order), FP64:
+    the Moebius transform, then brute-force superset sums with that index's
+    exact weights. ``interaction(v, d, l, "fsi")`` equals ``fsi(v, d, l)``."""
+    if not (1 <= l <= d):
+        raise ValueError("need 1 <= l <= d")
+    return _superset_weighted(v, d, l, index_weight_table_f64(index, d, l))
