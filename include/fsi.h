@@ -80,6 +80,32 @@ typedef enum {
   FSI_ALGO_TWO_PASS = 2
 } fsi_algo;
 
+/* Interaction index computed by a plan. Every index here is linear in v and,
+ * on the Moebius transform a, weights each superset T of S by a number that
+ * depends only on s = |S| and t = |T| (Appendix A), so all of them run through
+ * the same Moebius butterfly, counter sweep and final weight core:
+ *
+ *   I_S = sum_{T superset of S} W(s, t) a(T),   |S| <= l,
+ *
+ *   FSI   W = 1 at t = s; w(s, t) of Eq. 7 for t > l, s >= 1; else 0
+ *   STII  W = [t = s] for s < l; 1 / C(t, l) for s = l (Shapley-Taylor,
+ *         the cited definition: higher-order Moebius mass split evenly over
+ *         the top-order subsets)
+ *   SII   W = 1 / (t - s + 1)     (Shapley interaction index)
+ *   KSII  W = [t = 0] for s = 0; for s >= 1
+ *         sum_{j=0}^{min(l-s, t-s)} B_j C(t-s, j) / (t-s-j+1), B_j the
+ *         Bernoulli numbers with B_1 = -1/2 (k-Shapley interaction index)
+ *   BII   W = 2^-(t - s)          (Banzhaf interaction index)
+ *
+ * The weights are evaluated in binary128 and rounded once to FP64. */
+typedef enum {
+  FSI_INDEX_FSI = 0,
+  FSI_INDEX_STII = 1,
+  FSI_INDEX_SII = 2,
+  FSI_INDEX_KSII = 3,
+  FSI_INDEX_BII = 4
+} fsi_index;
+
 typedef struct {
   int32_t dtype;                 /* fsi_dtype, default FSI_DTYPE_F64         */
   int32_t precision;             /* fsi_precision, default FSI_PREC_AUTO     */
@@ -89,7 +115,8 @@ typedef struct {
   int32_t autotune;              /* 1 = time candidate schedules at plan     */
                                  /* time (see fsi_schedule), keep the best   */
   int32_t kernel;                /* fsi_kernel, default FSI_KERNEL_AUTO      */
-  int32_t reserved[3];           /* must be 0                                */
+  int32_t index;                 /* fsi_index, default FSI_INDEX_FSI         */
+  int32_t reserved[2];           /* must be 0                                */
 } fsi_plan_opts;
 
 /* Tile kernel of the fused algorithm. The register-phase kernel (tiles of

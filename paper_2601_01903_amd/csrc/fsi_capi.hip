@@ -145,8 +145,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   fsi_plan_opts opts;
   fsi_default_opts(&opts);
   if (opts_in) opts = *opts_in;
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 2; ++i)
     if (opts.reserved[i] != 0) return fail(FSI_ERR_INVALID_ARG, "reserved option fields must be 0");
+  if (opts.index < FSI_INDEX_FSI || opts.index > FSI_INDEX_BII)
+    return fail(FSI_ERR_INVALID_ARG, "unknown interaction index");
   if (opts.kernel < FSI_KERNEL_AUTO || opts.kernel > FSI_KERNEL_REGISTER)
     return fail(FSI_ERR_INVALID_ARG, "unknown kernel");
   if (opts.dtype != FSI_DTYPE_F64 && opts.dtype != FSI_DTYPE_F32)
@@ -207,7 +209,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       }
       int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
       if (!want_fast && opts.tile_bits == 0) b = std::max(1, b + sc.tb_shift);
-      std::string err = build_class(dh[i], lh[i], b, algo, &C);
+      std::string err = build_class(dh[i], lh[i], b, algo, opts.index, &C);
       if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
       const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
                                              ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));

@@ -90,11 +90,11 @@ struct ClassHost {
 int64_t num_outputs(int d, int l);
 std::vector<uint32_t> canonical_masks(int d, int l);
 // Exact W(s, t) of the operator, rounded once to double (see fsi_tables.cpp).
-double weight_full(int s, int t, int l);
+double weight_full(int s, int t, int l, int index);
 // Largest sweep state of an in-tile sweep over b bits, in entries.
 int64_t sweep_peak_entries(int b, int l);
 // Builds all tables for one class; returns "" or an error message.
-std::string build_class(int d, int l, int b, int algo, ClassHost* out);
+std::string build_class(int d, int l, int b, int algo, int index, ClassHost* out);
 // Output slots per thread the register-phase kernel needs for (d, l), or -1.
 int fast_output_slots(int d, int l);
 // Builds the register-phase kernel tables from an already built fused class

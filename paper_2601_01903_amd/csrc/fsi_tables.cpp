@@ -6,6 +6,7 @@
 #include <cstring>
 #include <map>
 
+#include "../../include/fsi.h"
 #include "fsi_internal.h"
 #include "fsi_kernels.h"
 #include "fsi_tile11.h"
@@ -22,21 +23,62 @@ int64_t binom(int n, int k) {
   return (int64_t)r;
 }
 
-// W(s, t): the coefficient of a(T) in E_S for |S| = s, |T| = t, T superset
-// of S (closed form Eq. 3 + Eq. 4):
+// FSI weight of Eq. 3 + Eq. 4: the coefficient of a(T) in E_S for |S| = s,
+// |T| = t, T superset of S:
 //   1                 if t == s      (the Moebius term a(S))
 //   w(s, t) of Eq. 7  if t > l, s >= 1
 //   0                 otherwise.
 // w(s, t) = (-1)^(l-s) * s/(l+s) * C(l,s) * C(t-1,l) / C(t+l-1,l+s), whose
 // numerator and denominator are exact 64-bit integers for d, l <= 30; the
 // quotient is taken in binary128 (113-bit significand).
-__float128 weight_q(int s, int t, int l) {
+__float128 weight_fsi(int s, int t, int l) {
   if (t == s) return 1;
   if (!(t > l && s >= 1)) return 0;
   __int128 num = (__int128)s * binom(l, s) * binom(t - 1, l);
   __int128 den = (__int128)(l + s) * binom(t + l - 1, l + s);
   __float128 q = (__float128)num / (__float128)den;
   return ((l - s) & 1) ? -q : q;
+}
+
+// Bernoulli number B_j (B_1 = -1/2) from sum_{i=0}^{m} C(m+1, i) B_i = 0,
+// in binary128; j <= 30 (B_30 is about 6e8, far inside its exact range).
+__float128 bernoulli_q(int j) {
+  __float128 B[kMaxD + 1];
+  B[0] = 1;
+  for (int m = 1; m <= j; ++m) {
+    __float128 acc = 0;
+    for (int i = 0; i < m; ++i) acc += (__float128)binom(m + 1, i) * B[i];
+    B[m] = -acc / (__float128)(m + 1);
+  }
+  return B[j];
+}
+
+// W(s, t) of the plan's interaction index on the Moebius transform (the
+// cardinal weights of Appendix A's indices; fsi.h lists them), for t >= s.
+__float128 weight_q(int s, int t, int l, int index) {
+  if (t < s) return 0;
+  switch (index) {
+    case FSI_INDEX_STII:
+      if (s < l) return t == s ? 1 : 0;
+      return (__float128)1 / (__float128)binom(t, l);
+    case FSI_INDEX_SII:
+      return (__float128)1 / (__float128)(t - s + 1);
+    case FSI_INDEX_BII: {
+      __float128 w = 1;
+      for (int i = 0; i < t - s; ++i) w *= (__float128)0.5;
+      return w;
+    }
+    case FSI_INDEX_KSII: {
+      if (s == 0) return t == 0 ? 1 : 0;
+      const int n = t - s;
+      __float128 acc = 0;
+      for (int j = 0; j <= std::min(l - s, n); ++j)
+        acc += bernoulli_q(j) * (__float128)binom(n, j) / (__float128)(n - j + 1);
+      return acc;
+    }
+    default:
+      return weight_fsi(s, t, l);
+  }
 }
 
 // Precontracted high-site weight (the Moebius cores of the h high sites
@@ -46,10 +88,10 @@ __float128 weight_q(int s, int t, int l) {
 //   lambda = sum_{m=0}^{h-q} C(h-q, m) (-1)^(q+m-u) W(s, t_L + q + m),
 // i.e. the sum over all high supersets T_H of S_H union U_H of
 // (-1)^(|T_H|-|U_H|) W(s, t_L + |T_H|).
-__float128 lambda_q(int s, int tL, int q, int u, int h, int l) {
+__float128 lambda_q(int s, int tL, int q, int u, int h, int l, int index) {
   __float128 acc = 0;
   for (int m = 0; m <= h - q; ++m) {
-    __float128 term = (__float128)binom(h - q, m) * weight_q(s, tL + q + m, l);
+    __float128 term = (__float128)binom(h - q, m) * weight_q(s, tL + q + m, l, index);
     acc += ((q + m - u) & 1) ? -term : term;
   }
   return acc;
@@ -59,7 +101,7 @@ int popc(uint64_t x) { return __builtin_popcountll(x); }
 
 }  // namespace
 
-double weight_full(int s, int t, int l) { return (double)weight_q(s, t, l); }
+double weight_full(int s, int t, int l, int index) { return (double)weight_q(s, t, l, index); }
 
 int64_t num_outputs(int d, int l) {
   if (!(1 <= l && l <= d && d <= kMaxD)) return -1;
@@ -98,7 +140,7 @@ int64_t sweep_peak_entries(int b, int l) {
   return peak;
 }
 
-std::string build_class(int d, int l, int b, int algo, ClassHost* C) {
+std::string build_class(int d, int l, int b, int algo, int index, ClassHost* C) {
   if (!(1 <= l && l <= d && d <= kMaxD)) return "invalid (d, l)";
   if (!(1 <= b && b <= kMaxTileBits && b <= d)) return "invalid tile bits";
   const int h = d - b;
@@ -199,11 +241,11 @@ std::string build_class(int d, int l, int b, int algo, ClassHost* C) {
             const bool ok = j <= u && (sH - j) <= (h - u);
             const int q = u + sH - j;
             for (int tL = sL; tL <= b; ++tL)
-              blk[slot * (b + 1) + tL] = ok ? (double)lambda_q(s, tL, q, u, h, l) : 0.0;
+              blk[slot * (b + 1) + tL] = ok ? (double)lambda_q(s, tL, q, u, h, l, index) : 0.0;
           }
         } else {
           for (int tL = sL; tL <= b; ++tL)
-            blk[sH * (b + 1) + tL] = (double)weight_q(s, tL + u, l);
+            blk[sH * (b + 1) + tL] = (double)weight_q(s, tL + u, l, index);
         }
       }
     }
