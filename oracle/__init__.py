@@ -28,6 +28,8 @@ from .fsi_oracle import (  # noqa: F401
     weight_table_f64,
 )
 
+from .forest import forest_value_at, forest_values  # noqa: F401
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "fsi_oracle_c.c")
 _LIB = os.path.join(_HERE, "_build", "liboracle.so")
