@@ -15,7 +15,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libfsi_mi355x.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["fsi_kernels.hip", "fsi_tile11.hip", "fsi_capi.hip"]
+HIP_SOURCES = ["fsi_kernels.hip", "fsi_tile11.hip", "fsi_capi.hip", "fsi_forest.hip"]
 CXX_SOURCES = ["fsi_tables.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I" + os.path.join(os.path.dirname(HERE), "include")]

@@ -59,6 +59,11 @@ bool device_is_gfx950(int* dev, int* n_cu, std::string* why) {
 
 }  // namespace
 
+namespace fsi {
+void record_error(const std::string& msg) { g_err = msg; }
+bool gfx950_device(int* dev, int* n_cu, std::string* why) { return device_is_gfx950(dev, n_cu, why); }
+}  // namespace fsi
+
 struct fsi_batch_plan_s {
   int n = 0, dtype = FSI_DTYPE_F64, prec = PREC_F64, algo = ALGO_FUSED;
   int device = 0, n_cu = 256;

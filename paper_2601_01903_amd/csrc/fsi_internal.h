@@ -89,6 +89,11 @@ struct ClassHost {
 
 int64_t num_outputs(int d, int l);
 std::vector<uint32_t> canonical_masks(int d, int l);
+// Message behind fsi_last_error() (thread-local), for entry points outside
+// the main C-ABI source.
+void record_error(const std::string& msg);
+// True if the current HIP device is a gfx950; else *why says what it is.
+bool gfx950_device(int* dev, int* n_cu, std::string* why);
 // Exact W(s, t) of the operator, rounded once to double (see fsi_tables.cpp).
 double weight_full(int s, int t, int l, int index);
 // Largest sweep state of an in-tile sweep over b bits, in entries.

@@ -31,7 +31,8 @@ EXPORTS = ["fsi_default_opts", "fsi_num_outputs", "fsi_plan", "fsi_plan_ex",
            "fsi_mobius", "fsi_plan_batched", "fsi_batch_plan_destroy",
            "fsi_batch_offsets", "fsi_apply_batched", "fsi_apply_batched_nograph",
            "fsi_batch_num_stages", "fsi_apply_batched_stage", "fsi_plan_schedule",
-           "fsi_batch_schedule", "fsi_last_error"]
+           "fsi_batch_schedule", "fsi_last_error",
+           "fsi_forest_create", "fsi_forest_destroy", "fsi_forest_values"]
 
 
 class FsiError(RuntimeError):
@@ -92,6 +93,11 @@ def load() -> ctypes.CDLL:
     lib.fsi_apply_batched_stage.argtypes = [vp, vp, vp, i32, vp]
     lib.fsi_plan_schedule.argtypes = [vp, P(Schedule)]
     lib.fsi_batch_schedule.argtypes = [vp, P(Schedule)]
+    lib.fsi_forest_create.argtypes = [i32, i32, P(ctypes.c_int32), i32, P(ctypes.c_int32),
+                                      P(ctypes.c_double), P(ctypes.c_int32), P(ctypes.c_int32),
+                                      P(ctypes.c_double), i32, P(vp)]
+    lib.fsi_forest_destroy.argtypes = [vp]
+    lib.fsi_forest_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
     lib.fsi_last_error.argtypes = []
     lib.fsi_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -273,3 +279,60 @@ class BatchPlan:
         _check(load().fsi_apply_batched_stage(self._h, ctypes.c_void_p(values.data_ptr()),
                                               ctypes.c_void_p(out.data_ptr()), int(stage),
                                               _stream_handle(stream)), "fsi_apply_batched_stage")
+
+
+class Forest:
+    """fsi_forest_create / fsi_forest_values: the interventional value function
+    of a tree ensemble over all 2^d coalitions (include/fsi_forest.h).
+
+    Node arrays (host, any integer/float dtype convertible): feature (< 0 marks
+    a leaf), threshold, left, right, value; roots holds each tree's root."""
+
+    def __init__(self, d: int, roots, feature, threshold, left, right, value, max_bg: int = 1):
+        import numpy as np
+        lib = load()
+        self.d, self.max_bg = d, max_bg
+        self._arrs = [np.ascontiguousarray(a, dtype=t) for a, t in (
+            (roots, np.int32), (feature, np.int32), (threshold, np.float64),
+            (left, np.int32), (right, np.int32), (value, np.float64))]
+        r, f, th, lf, rt, val = self._arrs
+        n_nodes = f.size
+        if not (th.size == lf.size == rt.size == val.size == n_nodes):
+            raise ValueError("node arrays differ in length")
+        P = ctypes.POINTER
+        self._h = ctypes.c_void_p()
+        _check(lib.fsi_forest_create(
+            d, r.size, r.ctypes.data_as(P(ctypes.c_int32)), n_nodes,
+            f.ctypes.data_as(P(ctypes.c_int32)), th.ctypes.data_as(P(ctypes.c_double)),
+            lf.ctypes.data_as(P(ctypes.c_int32)), rt.ctypes.data_as(P(ctypes.c_int32)),
+            val.ctypes.data_as(P(ctypes.c_double)), max_bg, ctypes.byref(self._h)),
+            "fsi_forest_create")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            load().fsi_forest_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def values(self, x: torch.Tensor, bg: torch.Tensor, dtype: str = "f64",
+               out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """v over all 2^d coalitions for the explained point x (d FP64 values)
+        and background rows bg (n_bg x d FP64), both device tensors."""
+        _check_tensor(x, self.d, torch.float64, "x")
+        if bg.dim() != 2 or bg.shape[1] != self.d:
+            raise ValueError("bg must have shape (n_bg, d)")
+        _check_tensor(bg, bg.numel(), torch.float64, "bg")
+        dt = _TORCH_DTYPE[dtype]
+        if out is None:
+            out = torch.empty(1 << self.d, dtype=dt, device=x.device)
+        _check_tensor(out, 1 << self.d, dt, "out")
+        _check(load().fsi_forest_values(self._h, ctypes.c_void_p(x.data_ptr()), int(bg.shape[0]),
+                                        ctypes.c_void_p(bg.data_ptr()), DTYPES[dtype],
+                                        ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+               "fsi_forest_values")
+        return out

@@ -71,3 +71,55 @@ def test_plan_without_gfx950_is_unsupported():
     h = ctypes.c_void_p()
     assert lib.fsi_plan(8, 2, ctypes.byref(h)) == 2
     assert lib.fsi_last_error()
+
+
+def _forest_call(d, roots, feature, threshold, left, right, value, max_bg=1):
+    import numpy as np
+    lib = fsi.load()
+    P = ctypes.POINTER
+    arrs = [np.ascontiguousarray(a, dtype=t) for a, t in (
+        (roots, np.int32), (feature, np.int32), (threshold, np.float64),
+        (left, np.int32), (right, np.int32), (value, np.float64))]
+    r, f, th, lf, rt, val = arrs
+    h = ctypes.c_void_p()
+    st = lib.fsi_forest_create(d, r.size, r.ctypes.data_as(P(ctypes.c_int32)), f.size,
+                               f.ctypes.data_as(P(ctypes.c_int32)),
+                               th.ctypes.data_as(P(ctypes.c_double)),
+                               lf.ctypes.data_as(P(ctypes.c_int32)),
+                               rt.ctypes.data_as(P(ctypes.c_int32)),
+                               val.ctypes.data_as(P(ctypes.c_double)), max_bg, ctypes.byref(h))
+    return st, h
+
+
+def test_forest_validation_before_device_use():
+    """Malformed forests are rejected on the host (they could otherwise send
+    a walk out of bounds or around a cycle)."""
+    ok = dict(roots=[0], feature=[0, -1, -1], threshold=[0.5, 0, 0], left=[1, 0, 0],
+              right=[2, 0, 0], value=[0, 1, 2])
+    bad = [
+        dict(ok, d=0), dict(ok, d=31),
+        dict(ok, roots=[3]),                                   # root out of range
+        dict(ok, left=[7, 0, 0]),                              # child out of range
+        dict(ok, right=[-1, 0, 0]),
+        dict(ok, feature=[4, -1, -1]),                         # feature >= d
+        dict(ok, threshold=[float("nan"), 0, 0]),
+        dict(ok, feature=[0, 1, -1], left=[1, 0, 0], right=[2, 1, 0]),   # 1 -> 1 cycle
+        dict(ok, max_bg=0), dict(ok, max_bg=5000),
+    ]
+    # a chain of 65 splits is deeper than the walk allows
+    n = 66
+    chain = dict(roots=[0], feature=[0] * 65 + [-1], threshold=[0.5] * 65 + [0],
+                 left=list(range(1, 66)) + [0], right=list(range(1, 66)) + [0],
+                 value=[0.0] * n)
+    bad.append(chain)
+    for case in bad:
+        kw = dict(ok)
+        kw.update(case)
+        d = kw.pop("d", 4)
+        max_bg = kw.pop("max_bg", 1)
+        st, h = _forest_call(d, max_bg=max_bg, **kw)
+        assert st == 1, case
+        assert h.value is None
+    lib = fsi.load()
+    assert lib.fsi_forest_destroy(None) == 0
+    assert lib.fsi_forest_values(None, None, 1, None, 0, None, None) == 1
