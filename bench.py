@@ -78,6 +78,134 @@ def normwise(x, ref):
     return float(np.max(np.abs(x - ref)) / den) if den else float(np.max(np.abs(x)))
 
 
+def heap_forest(g):
+    """Node arrays of a games.TreeGame (full binary trees in heap order)."""
+    n_int = (1 << g.depth) - 1
+    n_tree = n_int + (1 << g.depth)
+    K = g.feat.shape[0]
+    feature = np.full(K * n_tree, -1, dtype=np.int32)
+    threshold = np.zeros(K * n_tree)
+    left = np.zeros(K * n_tree, dtype=np.int32)
+    right = np.zeros(K * n_tree, dtype=np.int32)
+    value = np.zeros(K * n_tree)
+    idx = np.arange(n_int)
+    for k in range(K):
+        o = k * n_tree
+        feature[o:o + n_int] = g.feat[k]
+        threshold[o:o + n_int] = g.thr[k]
+        left[o:o + n_int] = o + 2 * idx + 1
+        right[o:o + n_int] = o + 2 * idx + 2
+        value[o + n_int:o + n_tree] = g.leaf[k]
+    return np.arange(K, dtype=np.int32) * n_tree, feature, threshold, left, right, value
+
+
+def bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads):
+    """Generate the value functions of the even (tree-game) instances on the
+    GPU straight into the FSI input buffer, time that step and the chain
+    (generation + batched FSI), check it against the seeded generator and the
+    oracle, and time one forest with 100 background points."""
+    import torch
+    import games
+    import oracle
+    from paper_2601_01903_amd import Forest
+    dev = x32.device
+    tree_ids = list(range(0, n, 2))
+    forests, xs, bgs = [], [], []
+    for i in tree_ids:
+        g = games.tree_game(d, 200, 6, games.rng_for(games.CFG_D20_BATCH, i))
+        forests.append(Forest(d, *heap_forest(g), max_bg=100))
+        xs.append(torch.as_tensor(g.x).to(dev))
+        bgs.append(torch.as_tensor(g.b[None, :].copy()).to(dev))
+        if i == 0:
+            g0 = g
+    xv = x32.clone()
+
+    def gen():
+        for k, i in enumerate(tree_ids):
+            forests[k].values(xs[k], bgs[k], dtype="f32", out=xv[i * N:(i + 1) * N])
+
+    work = torch.empty(N, dtype=torch.float64, device=dev)
+
+    def gen_mobius():
+        for k, i in enumerate(tree_ids):
+            forests[k].values(xs[k], bgs[k], dtype="f32", out=xv[i * N:(i + 1) * N],
+                              method="mobius", work=work)
+
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    reps = max(1, args.steps // 4)
+
+    def timed(fn, with_fsi=False):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+            if with_fsi:
+                bp32.apply(xv, out32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    mob_ms = timed(gen_mobius)
+    chain_mob_ms = timed(gen_mobius, with_fsi=True)
+    got_m = xv.cpu().numpy()
+    mob_err = max(float(np.max(np.abs(got_m[i * N:(i + 1) * N] - vals32[i * N:(i + 1) * N]))
+                        / np.max(np.abs(vals32[i * N:(i + 1) * N]))) for i in tree_ids)
+    gen_ms = timed(gen)
+    chain_ms = timed(gen, with_fsi=True)
+    got = xv.cpu().numpy()
+    # the walked tree games equal the seeded inputs (same order of sums)
+    same = all(np.array_equal(got[i * N:(i + 1) * N], vals32[i * N:(i + 1) * N]) for i in tree_ids)
+    forest0 = heap_forest(g0)
+    rng = np.random.default_rng(5)
+    samp = [int(S) for S in rng.integers(0, N, size=200)]
+    t0 = time.perf_counter()
+    ref = [oracle.forest_value_at(S, d, *forest0, g0.x, g0.b[None, :]) for S in samp]
+    cpu_el = time.perf_counter() - t0
+    exact = all(got[S] == np.float32(r) for S, r in zip(samp, ref))
+    # interventional game over 100 background points (one forest)
+    rbg = torch.as_tensor(np.random.default_rng(6).uniform(size=(100, d))).to(dev)
+    vb = torch.empty(N, dtype=torch.float32, device=dev)
+    forests[0].values(xs[0], rbg, dtype="f32", out=vb)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        forests[0].values(xs[0], rbg, dtype="f32", out=vb)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    bg_ms = e0.elapsed_time(e1) / reps
+    vb_h = vb.cpu().numpy()
+    rb = rbg.cpu().numpy()
+    exact_bg = all(vb_h[S] == np.float32(oracle.forest_value_at(S, d, *forest0, g0.x, rb))
+                   for S in samp[:8])
+    for F in forests:
+        F.close()
+    visits = 200 * 6   # internal nodes on each (tree) walk of a depth-6 forest
+    rec = {"instances": len(tree_ids), "trees": 200, "depth": 6, "d": d,
+           "ms_per_step": gen_ms,
+           "coalitions_per_s": len(tree_ids) * N / (gen_ms * 1e-3),
+           "node_visits_per_s": len(tree_ids) * N * visits / (gen_ms * 1e-3),
+           "chain_ms_per_step": chain_ms,
+           "chain_note": "generate the 128 tree games, then the batched FSI of all 256 instances",
+           "equals_seeded_inputs": bool(same), "oracle_sample_exact": bool(exact),
+           "mobius_route": {"ms_per_step": mob_ms,
+                            "coalitions_per_s": len(tree_ids) * N / (mob_ms * 1e-3),
+                            "chain_ms_per_step": chain_mob_ms,
+                            "max_rel_diff_vs_seeded_inputs": mob_err},
+           "multi_background": {"n_bg": 100, "ms": bg_ms,
+                                "coalition_values_per_s": N / (bg_ms * 1e-3),
+                                "oracle_sample_exact": bool(exact_bg)},
+           "cpu_oracle": {"coalitions_per_s": len(samp) / cpu_el, "cores": 1, "kind": "oracle",
+                          "sample": f"{len(samp)} coalitions of instance 0, single-coalition walk"}}
+    log(f"value functions (Moebius route): {mob_ms:.3f} ms, chain {chain_mob_ms:.3f} ms, "
+        f"max rel diff {mob_err:.2e}")
+    log(f"value functions: {gen_ms:.3f} ms for {len(tree_ids)} forests "
+        f"({rec['coalitions_per_s']:.3e} coalitions/s), chain {chain_ms:.3f} ms, "
+        f"100 backgrounds {bg_ms:.3f} ms, exact {same and exact and exact_bg}")
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +218,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--check-sample", type=int, default=4)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-forest", action="store_true",
+                    help="skip generating the tree games' value functions on the GPU")
     ap.add_argument("--no-indices", action="store_true",
                     help="skip the other interaction indices (SII, k-SII, STII, BII) on the workload")
     ap.add_argument("--no-autotune", action="store_true",
@@ -205,6 +335,11 @@ def main():
             bpi.close()
             log(f"index {index}: {ims:.3f} ms/step, oracle sample err {max(ierr):.2e}")
 
+    # ---- value functions of the tree-game half generated on the GPU ----
+    vfun = None
+    if not args.no_forest:
+        vfun = bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads)
+
     # ---- FP64 paths on the same instances ----
     fp64 = None
     errs = None
@@ -317,6 +452,7 @@ def main():
         "speedup_vs_batched_fp64": (fp64["batched_ms_per_step"] / ms_per_step) if fp64 else None,
         "errors": errs,
         "indices": indices,
+        "value_function": vfun,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

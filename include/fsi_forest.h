@@ -65,6 +65,36 @@ fsi_status fsi_forest_values(fsi_forest_t forest, const double* x_dev, int n_bg,
                              const double* bg_dev, int dtype, void* v_dev,
                              hipStream_t stream);
 
+/* The Moebius transform of v (the coefficients a the FSI operator starts
+ * from, Sec. 2.2), without forming v: a leaf of a tree is reached at z_b(S)
+ * iff every test on its root path passes, so its indicator is a product over
+ * the path's features f of (beta_f + [f in S] (alpha_f - beta_f)), with
+ * alpha_f (beta_f) = 1 if x (bg_b) passes every test on f of that path. Its
+ * Moebius coefficients are +-value on the sets I u Q, I = {f: beta_f = 0},
+ * Q a subset of {f: beta_f = 1, alpha_f = 0}, sign (-1)^|Q| (none if some f
+ * in I has alpha_f = 0). One GPU thread per (background, root-to-leaf path)
+ * adds value / n_bg at each of them.
+ *  a_dev: 2^d FP64 (device, caller-owned); zeroed by the call, then summed
+ *         with FP64 atomics, so the result is not bitwise repeatable (equal
+ *         to rounding).
+ * Arguments otherwise as fsi_forest_values. FSI_ERR_UNSUPPORTED if the
+ * forest has more than 2^26 root-to-leaf paths, or paths of more than 24
+ * splits while d > 24 (a path with k free features adds 2^k terms). */
+fsi_status fsi_forest_mobius(fsi_forest_t forest, const double* x_dev, int n_bg,
+                             const double* bg_dev, double* a_dev, hipStream_t stream);
+
+/* v through the Moebius route: fsi_forest_mobius into work_dev, then the
+ * subset-sum (zeta) butterfly v(S) = sum_{R subset of S} a(R) in FP64 passes
+ * of 5 index bits, the last pass writing v_dev in dtype.
+ *  work_dev: 2^d FP64 (device, caller-owned); may equal v_dev when dtype is
+ *            FSI_DTYPE_F64, must differ from it for FSI_DTYPE_F32.
+ * Equal to fsi_forest_values up to FP64 rounding (the sums run in another
+ * order); much faster for shallow trees (work per path is 2^(free
+ * features), not 2^d walks). */
+fsi_status fsi_forest_values_mobius(fsi_forest_t forest, const double* x_dev, int n_bg,
+                                    const double* bg_dev, double* work_dev, int dtype,
+                                    void* v_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -131,6 +131,99 @@ walk_kernel(const Node* __restrict__ prep, const double* __restrict__ value,
 
 constexpr int kWalkKP = 2;
 
+// ---- Moebius route ----
+// A leaf of a tree is reached at z_b(S) iff every test on its root path
+// passes. With alpha_f (beta_f) = [x (bg_b) passes every test on feature f of
+// the path], the leaf's indicator is prod_f (beta_f + [f in S](alpha_f -
+// beta_f)), whose Moebius coefficients sit on R = I u Q: I = {f: beta_f = 0}
+// (unreachable if some f in I has alpha_f = 0), Q any subset of
+// Fr = {f: beta_f = 1, alpha_f = 0}, with sign (-1)^|Q|. One thread per
+// (background, path) adds value / B * (-1)^|Q| at every such R.
+__global__ void __launch_bounds__(kThreads)
+fill_kernel(double* __restrict__ a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads)
+    a[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(kThreads)
+mobius_scatter_kernel(const int32_t* __restrict__ path_off, const int32_t* __restrict__ steps,
+                      const int32_t* __restrict__ path_leaf, int n_paths,
+                      const int32_t* __restrict__ feature, const double* __restrict__ threshold,
+                      const double* __restrict__ value, int d, const double* __restrict__ x,
+                      const double* __restrict__ bg, int n_bg, double* __restrict__ a) {
+  const int64_t total = (int64_t)n_bg * n_paths;
+  for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * kThreads) {
+    const int b = (int)(i / n_paths);
+    const int p = (int)(i - (int64_t)b * n_paths);
+    const double* z = bg + (int64_t)b * d;
+    uint32_t seen = 0, aok = ~0u, bok = ~0u;
+    for (int s = path_off[p]; s < path_off[p + 1]; ++s) {
+      const int e = steps[s];
+      const int node = e >> 1;
+      const bool dir = e & 1;
+      const int f = feature[node];
+      const double th = threshold[node];
+      const uint32_t bit = 1u << f;
+      seen |= bit;
+      if ((x[f] >= th) != dir) aok &= ~bit;
+      if ((z[f] >= th) != dir) bok &= ~bit;
+    }
+    const uint32_t I = seen & ~bok;
+    if (I & ~aok) continue;                        // never reached
+    const uint32_t Fr = seen & bok & ~aok;
+    const double c = value[path_leaf[p]] / (double)n_bg;
+    uint32_t Q = 0;
+    do {
+      atomicAdd(a + (I | Q), (__popc(Q) & 1) ? -c : c);
+      Q = (Q - Fr) & Fr;
+    } while (Q != 0);
+  }
+}
+
+// Subset sums (zeta transform, the inverse of the Moebius butterfly) over
+// the NB bits [bit0, bit0 + NB) of the index: each thread owns the 2^NB
+// entries of one column in registers. The last pass may write the result in
+// the output dtype instead of in place.
+template <int NB, typename OutT>
+__global__ void __launch_bounds__(kThreads)
+zeta_pass_kernel(double* __restrict__ a, int d, int bit0, OutT* __restrict__ out) {
+  const int64_t cols = (int64_t)1 << (d - NB);
+  const int64_t low = ((int64_t)1 << bit0) - 1;
+  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < cols;
+       t += (int64_t)gridDim.x * kThreads) {
+    const int64_t base = (t & low) | ((t >> bit0) << (bit0 + NB));
+    double v[1 << NB];
+#pragma unroll
+    for (int k = 0; k < (1 << NB); ++k) v[k] = a[base + ((int64_t)k << bit0)];
+#pragma unroll
+    for (int bit = 0; bit < NB; ++bit)
+#pragma unroll
+      for (int k = 0; k < (1 << NB); ++k)
+        if (k & (1 << bit)) v[k] += v[k ^ (1 << bit)];
+#pragma unroll
+    for (int k = 0; k < (1 << NB); ++k) out[base + ((int64_t)k << bit0)] = (OutT)v[k];
+  }
+}
+
+template <typename OutT>
+void launch_zeta(double* a, int d, int bit0, int nb, OutT* out, hipStream_t st) {
+  const int64_t cols = (int64_t)1 << (d - nb);
+  const int grid = (int)std::min<int64_t>((cols + kThreads - 1) / kThreads, 8192);
+  switch (nb) {
+    case 1: zeta_pass_kernel<1, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
+    case 2: zeta_pass_kernel<2, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
+    case 3: zeta_pass_kernel<3, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
+    case 4: zeta_pass_kernel<4, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
+    default: zeta_pass_kernel<5, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
+  }
+}
+
+constexpr int kZetaBits = 5;        // bits per zeta pass
+constexpr int kMaxFreeSplits = 24;  // longest path the Moebius route expands
+constexpr int64_t kMaxPathSteps = (int64_t)1 << 26;
+
 }  // namespace forest
 }  // namespace fsi
 
@@ -146,6 +239,11 @@ struct fsi_forest_s {
   double* threshold = nullptr;
   double* value = nullptr;
   Node* prep = nullptr;
+  // root-to-leaf paths for the Moebius route (n_paths < 0: not available)
+  int n_paths = 0, max_path = 0;
+  int32_t* path_off = nullptr;
+  int32_t* steps = nullptr;        // node << 1 | went right
+  int32_t* path_leaf = nullptr;
 };
 
 namespace {
@@ -158,7 +256,8 @@ fsi_status ffail(fsi_status st, const std::string& msg) {
 void free_forest(fsi_forest_s* F) {
   if (!F) return;
   for (void* p : {(void*)F->feature, (void*)F->left, (void*)F->right, (void*)F->roots,
-                  (void*)F->threshold, (void*)F->value, (void*)F->prep})
+                  (void*)F->threshold, (void*)F->value, (void*)F->prep,
+                  (void*)F->path_off, (void*)F->steps, (void*)F->path_leaf})
     if (p) (void)hipFree(p);
   delete F;
 }
@@ -197,6 +296,46 @@ int forest_depth(int n_nodes, const int32_t* feature, const int32_t* left,
     best = std::max(best, depth[roots[k]]);
   }
   return best;
+}
+
+// Every root-to-leaf path (a leaf reached from several roots or along several
+// routes counts once per path). Returns false if the paths exceed the caps.
+bool enumerate_paths(const int32_t* feature, const int32_t* left, const int32_t* right,
+                     const int32_t* roots, int n_trees, std::vector<int32_t>* off,
+                     std::vector<int32_t>* steps, std::vector<int32_t>* leaf) {
+  off->assign(1, 0);
+  steps->clear();
+  leaf->clear();
+  std::vector<int32_t> path;
+  // explicit DFS: (node, next child to visit: 0 left, 1 right, 2 done)
+  std::vector<std::pair<int, int>> st;
+  for (int k = 0; k < n_trees; ++k) {
+    st.assign(1, {roots[k], 0});
+    path.clear();
+    while (!st.empty()) {
+      auto& top = st.back();
+      const int node = top.first;
+      if (feature[node] < 0) {
+        steps->insert(steps->end(), path.begin(), path.end());
+        off->push_back((int32_t)steps->size());
+        leaf->push_back(node);
+        if ((int64_t)steps->size() > kMaxPathSteps || (int64_t)leaf->size() >= ((int64_t)1 << 26))
+          return false;
+        st.pop_back();
+        if (!path.empty()) path.pop_back();
+        continue;
+      }
+      if (top.second == 2) {
+        st.pop_back();
+        if (!path.empty()) path.pop_back();
+        continue;
+      }
+      const int dir = top.second++;
+      path.push_back((node << 1) | dir);
+      st.push_back({dir ? right[node] : left[node], 0});
+    }
+  }
+  return true;
 }
 
 template <typename T>
@@ -258,6 +397,22 @@ fsi_status fsi_forest_create(int d, int n_trees, const int32_t* roots, int n_nod
     const size_t chunks = (size_t)((max_bg + kBgChunk - 1) / kBgChunk);
     e = hipMalloc((void**)&F->prep, chunks * (size_t)n_nodes * sizeof(Node));
   }
+  if (e == hipSuccess) {
+    std::vector<int32_t> poff, psteps, pleaf;
+    if (enumerate_paths(feat.data(), left, right, roots, n_trees, &poff, &psteps, &pleaf)) {
+      F->n_paths = (int)pleaf.size();
+      for (size_t p = 0; p + 1 < poff.size(); ++p)
+        F->max_path = std::max(F->max_path, poff[p + 1] - poff[p]);
+      if (std::min(F->max_path, d) > kMaxFreeSplits) F->n_paths = -1;
+    } else {
+      F->n_paths = -1;
+    }
+    if (F->n_paths > 0) {
+      e = upload(&F->path_off, poff.data(), poff.size());
+      if (e == hipSuccess) e = upload(&F->steps, psteps.data(), std::max<size_t>(psteps.size(), 1));
+      if (e == hipSuccess) e = upload(&F->path_leaf, pleaf.data(), pleaf.size());
+    }
+  }
   if (e != hipSuccess) {
     free_forest(F);
     return ffail(e == hipErrorOutOfMemory ? FSI_ERR_OUT_OF_MEMORY : FSI_ERR_HIP,
@@ -298,6 +453,58 @@ fsi_status fsi_forest_values(fsi_forest_t F, const double* x_dev, int n_bg, cons
     walk_kernel<float, kWalkKP><<<grid, kThreads, 0, stream>>>(
         F->prep, F->value, F->roots, F->n_trees, F->n_nodes, n_bg, F->max_depth, F->d,
         (float*)v_dev);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return ffail(FSI_ERR_HIP, std::string("forest launch: ") + hipGetErrorString(e));
+  return FSI_OK;
+}
+
+fsi_status fsi_forest_mobius(fsi_forest_t F, const double* x_dev, int n_bg, const double* bg_dev,
+                             double* a_dev, hipStream_t stream) {
+  if (!F) return ffail(FSI_ERR_INVALID_ARG, "forest is NULL");
+  if (!x_dev || !bg_dev || !a_dev) return ffail(FSI_ERR_INVALID_ARG, "null device pointer");
+  if (n_bg < 1 || n_bg > F->max_bg)
+    return ffail(FSI_ERR_INVALID_ARG, "need 1 <= n_bg <= the forest's max_bg");
+  if (((uintptr_t)a_dev | (uintptr_t)x_dev | (uintptr_t)bg_dev) & 15u)
+    return ffail(FSI_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+  if (F->n_paths < 0)
+    return ffail(FSI_ERR_UNSUPPORTED, "the Moebius route needs at most 2^26 root-to-leaf paths "
+                                      "of at most 24 splits (or d <= 24)");
+  const int64_t n_coal = (int64_t)1 << F->d;
+  fill_kernel<<<(int)std::min<int64_t>((n_coal + kThreads - 1) / kThreads, 8192), kThreads, 0,
+                stream>>>(a_dev, n_coal);
+  const int64_t work = (int64_t)n_bg * F->n_paths;
+  mobius_scatter_kernel<<<(int)std::min<int64_t>((work + kThreads - 1) / kThreads, 65535),
+                          kThreads, 0, stream>>>(F->path_off, F->steps, F->path_leaf, F->n_paths,
+                                                 F->feature, F->threshold, F->value, F->d, x_dev,
+                                                 bg_dev, n_bg, a_dev);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return ffail(FSI_ERR_HIP, std::string("forest launch: ") + hipGetErrorString(e));
+  return FSI_OK;
+}
+
+fsi_status fsi_forest_values_mobius(fsi_forest_t F, const double* x_dev, int n_bg,
+                                    const double* bg_dev, double* work_dev, int dtype,
+                                    void* v_dev, hipStream_t stream) {
+  if (!F) return ffail(FSI_ERR_INVALID_ARG, "forest is NULL");
+  if (!v_dev) return ffail(FSI_ERR_INVALID_ARG, "null device pointer");
+  if (dtype != FSI_DTYPE_F64 && dtype != FSI_DTYPE_F32)
+    return ffail(FSI_ERR_INVALID_ARG, "dtype must be FSI_DTYPE_F64 or FSI_DTYPE_F32");
+  if ((uintptr_t)v_dev & 15u) return ffail(FSI_ERR_INVALID_ARG, "device pointers must be 16-byte aligned");
+  if (dtype == FSI_DTYPE_F32 && (void*)work_dev == v_dev)
+    return ffail(FSI_ERR_INVALID_ARG, "an FP32 output needs its own FP64 workspace");
+  fsi_status st = fsi_forest_mobius(F, x_dev, n_bg, bg_dev, work_dev, stream);
+  if (st != FSI_OK) return st;
+  const int d = F->d;
+  for (int bit0 = 0; bit0 < d; bit0 += kZetaBits) {
+    const int nb = std::min(kZetaBits, d - bit0);
+    const bool last = bit0 + nb >= d;
+    if (last && dtype == FSI_DTYPE_F32)
+      launch_zeta<float>(work_dev, d, bit0, nb, (float*)v_dev, stream);
+    else if (last)
+      launch_zeta<double>(work_dev, d, bit0, nb, (double*)v_dev, stream);
+    else
+      launch_zeta<double>(work_dev, d, bit0, nb, work_dev, stream);
+  }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(FSI_ERR_HIP, std::string("forest launch: ") + hipGetErrorString(e));
   return FSI_OK;

@@ -32,7 +32,8 @@ EXPORTS = ["fsi_default_opts", "fsi_num_outputs", "fsi_plan", "fsi_plan_ex",
            "fsi_batch_offsets", "fsi_apply_batched", "fsi_apply_batched_nograph",
            "fsi_batch_num_stages", "fsi_apply_batched_stage", "fsi_plan_schedule",
            "fsi_batch_schedule", "fsi_last_error",
-           "fsi_forest_create", "fsi_forest_destroy", "fsi_forest_values"]
+           "fsi_forest_create", "fsi_forest_destroy", "fsi_forest_values",
+           "fsi_forest_mobius", "fsi_forest_values_mobius"]
 
 
 class FsiError(RuntimeError):
@@ -98,6 +99,8 @@ def load() -> ctypes.CDLL:
                                       P(ctypes.c_double), i32, P(vp)]
     lib.fsi_forest_destroy.argtypes = [vp]
     lib.fsi_forest_values.argtypes = [vp, vp, i32, vp, i32, vp, vp]
+    lib.fsi_forest_mobius.argtypes = [vp, vp, i32, vp, vp, vp]
+    lib.fsi_forest_values_mobius.argtypes = [vp, vp, i32, vp, vp, i32, vp, vp]
     lib.fsi_last_error.argtypes = []
     lib.fsi_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -319,20 +322,54 @@ class Forest:
         except Exception:
             pass
 
-    def values(self, x: torch.Tensor, bg: torch.Tensor, dtype: str = "f64",
-               out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        """v over all 2^d coalitions for the explained point x (d FP64 values)
-        and background rows bg (n_bg x d FP64), both device tensors."""
+    def _check_points(self, x, bg):
         _check_tensor(x, self.d, torch.float64, "x")
         if bg.dim() != 2 or bg.shape[1] != self.d:
             raise ValueError("bg must have shape (n_bg, d)")
         _check_tensor(bg, bg.numel(), torch.float64, "bg")
+
+    def values(self, x: torch.Tensor, bg: torch.Tensor, dtype: str = "f64",
+               out: Optional[torch.Tensor] = None, stream=None, method: str = "walk",
+               work: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """v over all 2^d coalitions for the explained point x (d FP64 values)
+        and background rows bg (n_bg x d FP64), both device tensors.
+        method "walk": every tree walked per coalition (fsi_forest_values);
+        "mobius": path-product Moebius coefficients, then subset sums
+        (fsi_forest_values_mobius; work is a 2^d FP64 scratch tensor)."""
+        self._check_points(x, bg)
         dt = _TORCH_DTYPE[dtype]
         if out is None:
             out = torch.empty(1 << self.d, dtype=dt, device=x.device)
         _check_tensor(out, 1 << self.d, dt, "out")
-        _check(load().fsi_forest_values(self._h, ctypes.c_void_p(x.data_ptr()), int(bg.shape[0]),
-                                        ctypes.c_void_p(bg.data_ptr()), DTYPES[dtype],
+        lib = load()
+        xp, bp = ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(bg.data_ptr())
+        if method == "walk":
+            _check(lib.fsi_forest_values(self._h, xp, int(bg.shape[0]), bp, DTYPES[dtype],
+                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+                   "fsi_forest_values")
+        elif method == "mobius":
+            if work is None:
+                work = out if dtype == "f64" else torch.empty(1 << self.d, dtype=torch.float64,
+                                                              device=x.device)
+            _check_tensor(work, 1 << self.d, torch.float64, "work")
+            _check(lib.fsi_forest_values_mobius(self._h, xp, int(bg.shape[0]), bp,
+                                                ctypes.c_void_p(work.data_ptr()), DTYPES[dtype],
+                                                ctypes.c_void_p(out.data_ptr()),
+                                                _stream_handle(stream)),
+                   "fsi_forest_values_mobius")
+        else:
+            raise ValueError("method must be 'walk' or 'mobius'")
+        return out
+
+    def mobius(self, x: torch.Tensor, bg: torch.Tensor, out: Optional[torch.Tensor] = None,
+               stream=None) -> torch.Tensor:
+        """The Moebius transform of v (2^d FP64) from leaf path products."""
+        self._check_points(x, bg)
+        if out is None:
+            out = torch.empty(1 << self.d, dtype=torch.float64, device=x.device)
+        _check_tensor(out, 1 << self.d, torch.float64, "out")
+        _check(load().fsi_forest_mobius(self._h, ctypes.c_void_p(x.data_ptr()), int(bg.shape[0]),
+                                        ctypes.c_void_p(bg.data_ptr()),
                                         ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
-               "fsi_forest_values")
+               "fsi_forest_mobius")
         return out

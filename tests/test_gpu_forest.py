@@ -3,8 +3,10 @@ against the CPU oracle (oracle/forest.py).
 
 Leaf selection is decided by exact FP64 comparisons on both sides and the
 leaf outputs are summed in the same order (backgrounds outer, trees inner,
-ascending), so the FP64 output must equal the oracle bit for bit and the FP32
-output must equal the oracle's value rounded once to FP32."""
+ascending), so the FP64 output of the walk must equal the oracle bit for bit and the FP32
+output must equal the oracle's value rounded once to FP32. The Moebius route
+sums +-leaf terms with FP64 atomics and then subset sums, so it is checked to
+1e-12 of max |v| (FP64) and 2e-7 (FP32 output)."""
 import ctypes
 
 import numpy as np
@@ -196,4 +198,74 @@ def test_forest_errors_on_device():
                                ctypes.c_void_p(bg3.data_ptr()), 7,
                                ctypes.c_void_p(v.data_ptr()), None)
     assert st == 1                              # unknown dtype
+    F.close()
+
+
+def gpu_mobius_route(d, forest, x, bgs, dtype="f64"):
+    fsi = fsi_mod()
+    bgs = np.atleast_2d(bgs)
+    F = fsi.Forest(d, *forest, max_bg=bgs.shape[0])
+    xt = torch.as_tensor(np.asarray(x, dtype=np.float64)).to(DEV)
+    bt = torch.as_tensor(np.ascontiguousarray(bgs, dtype=np.float64)).to(DEV)
+    a = F.mobius(xt, bt)
+    v = F.values(xt, bt, dtype=dtype, method="mobius")
+    torch.cuda.synchronize()
+    res = a.cpu().numpy(), v.cpu().numpy()
+    F.close()
+    return res
+
+
+@pytest.mark.parametrize("case", ["heap8", "heap14", "irregular11_bg5", "irregular12_bg40"])
+def test_mobius_route_matches_oracle(case):
+    say(f"[case] forest Moebius route {case}")
+    if case.startswith("heap"):
+        d = int(case[4:])
+        g = games.tree_game(d, 40, 5, games.rng_for(916, d))
+        forest, x, bgs = heap_forest(g), g.x, g.b[None, :]
+    else:
+        d, nb = (11, 5) if case.endswith("bg5") else (12, 40)
+        rng = np.random.default_rng(917 + d)
+        x, bgs = rng.uniform(size=d), rng.uniform(size=(nb, d))
+        forest = random_forest(d, 20, 7, rng, x, bgs)
+    v_ref = oracle.forest_values(d, *forest, x, bgs)
+    a_ref = oracle.mobius(v_ref)
+    scale = max(1.0, np.abs(v_ref).max())
+    a, v = gpu_mobius_route(d, forest, x, bgs)
+    assert np.max(np.abs(a - a_ref)) < 1e-12 * scale
+    assert np.max(np.abs(v - v_ref)) < 1e-12 * scale
+    _, v32 = gpu_mobius_route(d, forest, x, bgs, "f32")
+    assert np.max(np.abs(v32 - v_ref)) < 2e-7 * scale
+
+
+def test_mobius_route_d20_full_size():
+    say("[case] forest Moebius route d=20 200 depth-6 trees")
+    g, vgen = games.d20_tree(0)
+    forest = heap_forest(g)
+    a, v = gpu_mobius_route(20, forest, g.x, g.b)
+    scale = np.abs(vgen).max()
+    assert np.max(np.abs(v - vgen)) < 1e-12 * scale
+    rng = np.random.default_rng(918)
+    for S in rng.integers(0, 1 << 20, size=32):
+        assert abs(v[S] - oracle.forest_value_at(int(S), 20, *forest, g.x, g.b[None, :])) < 1e-12 * scale
+    # the Moebius coefficients of a tree game sit on sets of at most depth features
+    support = np.nonzero(np.abs(a) > 1e-12 * scale)[0]
+    assert max(bin(int(m)).count("1") for m in support) <= 6
+
+
+def test_mobius_route_refuses_long_paths():
+    fsi = fsi_mod()
+    d, k = 26, 25                               # one chain of 25 splits on 26 features
+    feature = np.array(list(range(k)) + [-1, -1], np.int32)
+    threshold = np.full(k + 2, 0.5)
+    left = np.array([k + 1] * k + [0, 0], np.int32)
+    right = np.array(list(range(1, k)) + [k, 0, 0], np.int32)
+    value = np.zeros(k + 2)
+    F = fsi.Forest(d, np.array([0], np.int32), feature, threshold, left, right, value)
+    x = torch.zeros(d, dtype=torch.float64, device=DEV)
+    bg = torch.zeros(1, d, dtype=torch.float64, device=DEV)
+    a = torch.zeros(16, dtype=torch.float64, device=DEV)
+    st = fsi.load().fsi_forest_mobius(F._h, ctypes.c_void_p(x.data_ptr()), 1,
+                                      ctypes.c_void_p(bg.data_ptr()),
+                                      ctypes.c_void_p(a.data_ptr()), None)
+    assert st == 2                              # FSI_ERR_UNSUPPORTED, nothing launched
     F.close()
