@@ -177,8 +177,13 @@ def bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads):
     bg_ms = e0.elapsed_time(e1) / reps
     vb_h = vb.cpu().numpy()
     rb = rbg.cpu().numpy()
-    exact_bg = all(vb_h[S] == np.float32(oracle.forest_value_at(S, d, *forest0, g0.x, rb))
-                   for S in samp[:8])
+    ref_bg = [oracle.forest_value_at(S, d, *forest0, g0.x, rb) for S in samp[:8]]
+    exact_bg = all(vb_h[S] == np.float32(r) for S, r in zip(samp[:8], ref_bg))
+    bg_mob_ms = timed(lambda: forests[0].values(xs[0], rbg, dtype="f32", out=vb, method="mobius",
+                                                work=work))
+    vb_h = vb.cpu().numpy()
+    bg_mob_err = max(abs(float(vb_h[S]) - r) for S, r in zip(samp[:8], ref_bg)) / max(
+        1.0, float(np.max(np.abs(vb_h))))
     for F in forests:
         F.close()
     visits = 200 * 6   # internal nodes on each (tree) walk of a depth-6 forest
@@ -195,14 +200,17 @@ def bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads):
                             "max_rel_diff_vs_seeded_inputs": mob_err},
            "multi_background": {"n_bg": 100, "ms": bg_ms,
                                 "coalition_values_per_s": N / (bg_ms * 1e-3),
-                                "oracle_sample_exact": bool(exact_bg)},
+                                "oracle_sample_exact": bool(exact_bg),
+                                "mobius_route_ms": bg_mob_ms,
+                                "mobius_route_oracle_sample_rel_err": bg_mob_err},
            "cpu_oracle": {"coalitions_per_s": len(samp) / cpu_el, "cores": 1, "kind": "oracle",
                           "sample": f"{len(samp)} coalitions of instance 0, single-coalition walk"}}
     log(f"value functions (Moebius route): {mob_ms:.3f} ms, chain {chain_mob_ms:.3f} ms, "
         f"max rel diff {mob_err:.2e}")
     log(f"value functions: {gen_ms:.3f} ms for {len(tree_ids)} forests "
         f"({rec['coalitions_per_s']:.3e} coalitions/s), chain {chain_ms:.3f} ms, "
-        f"100 backgrounds {bg_ms:.3f} ms, exact {same and exact and exact_bg}")
+        f"100 backgrounds {bg_ms:.3f} ms (Moebius route {bg_mob_ms:.3f} ms), "
+        f"exact {same and exact and exact_bg}")
     return rec
 
 

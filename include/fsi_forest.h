@@ -85,7 +85,8 @@ fsi_status fsi_forest_mobius(fsi_forest_t forest, const double* x_dev, int n_bg,
 
 /* v through the Moebius route: fsi_forest_mobius into work_dev, then the
  * subset-sum (zeta) butterfly v(S) = sum_{R subset of S} a(R) in FP64 passes
- * of 5 index bits, the last pass writing v_dev in dtype.
+ * (the low 10 index bits in LDS, then 5 bits per pass in registers), the last
+ * pass writing v_dev in dtype.
  *  work_dev: 2^d FP64 (device, caller-owned); may equal v_dev when dtype is
  *            FSI_DTYPE_F64, must differ from it for FSI_DTYPE_F32.
  * Equal to fsi_forest_values up to FP64 rounding (the sums run in another

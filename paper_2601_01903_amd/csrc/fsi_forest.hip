@@ -186,13 +186,17 @@ mobius_scatter_kernel(const int32_t* __restrict__ path_off, const int32_t* __res
 // the NB bits [bit0, bit0 + NB) of the index: each thread owns the 2^NB
 // entries of one column in registers. The last pass may write the result in
 // the output dtype instead of in place.
+// Small workgroups: a pass has only 2^(d-5) columns (32768 at d = 20), which
+// must still spread over every CU.
+constexpr int kZetaThreads = 64;
+
 template <int NB, typename OutT>
-__global__ void __launch_bounds__(kThreads)
-zeta_pass_kernel(double* __restrict__ a, int d, int bit0, OutT* __restrict__ out) {
+__global__ void __launch_bounds__(kZetaThreads)
+zeta_pass_kernel(double* a, int d, int bit0, OutT* out) {   // out may equal a
   const int64_t cols = (int64_t)1 << (d - NB);
   const int64_t low = ((int64_t)1 << bit0) - 1;
-  for (int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x; t < cols;
-       t += (int64_t)gridDim.x * kThreads) {
+  for (int64_t t = (int64_t)blockIdx.x * kZetaThreads + threadIdx.x; t < cols;
+       t += (int64_t)gridDim.x * kZetaThreads) {
     const int64_t base = (t & low) | ((t >> bit0) << (bit0 + NB));
     double v[1 << NB];
 #pragma unroll
@@ -207,16 +211,39 @@ zeta_pass_kernel(double* __restrict__ a, int d, int bit0, OutT* __restrict__ out
   }
 }
 
+// The low kZetaLow bits (or all d if fewer) in one pass: a workgroup loads a
+// contiguous tile of 2^lb entries into LDS, runs the lb butterfly levels
+// there and writes the tile back (coalesced both ways).
+constexpr int kZetaLow = 10;
+
+template <typename OutT>
+__global__ void __launch_bounds__(kThreads)
+zeta_low_kernel(const double* a, int lb, OutT* out) {        // out may equal a
+  __shared__ double t[1 << kZetaLow];
+  const int n = 1 << lb;
+  const int64_t base = (int64_t)blockIdx.x << lb;
+  for (int i = threadIdx.x; i < n; i += kThreads) t[i] = a[base + i];
+  __syncthreads();
+  for (int bit = 0; bit < lb; ++bit) {
+    for (int k = threadIdx.x; k < n / 2; k += kThreads) {
+      const int i0 = ((k >> bit) << (bit + 1)) | (k & ((1 << bit) - 1));
+      t[i0 | (1 << bit)] += t[i0];
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n; i += kThreads) out[base + i] = (OutT)t[i];
+}
+
 template <typename OutT>
 void launch_zeta(double* a, int d, int bit0, int nb, OutT* out, hipStream_t st) {
   const int64_t cols = (int64_t)1 << (d - nb);
-  const int grid = (int)std::min<int64_t>((cols + kThreads - 1) / kThreads, 8192);
+  const int grid = (int)std::min<int64_t>((cols + kZetaThreads - 1) / kZetaThreads, 32768);
   switch (nb) {
-    case 1: zeta_pass_kernel<1, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
-    case 2: zeta_pass_kernel<2, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
-    case 3: zeta_pass_kernel<3, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
-    case 4: zeta_pass_kernel<4, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
-    default: zeta_pass_kernel<5, OutT><<<grid, kThreads, 0, st>>>(a, d, bit0, out); break;
+    case 1: zeta_pass_kernel<1, OutT><<<grid, kZetaThreads, 0, st>>>(a, d, bit0, out); break;
+    case 2: zeta_pass_kernel<2, OutT><<<grid, kZetaThreads, 0, st>>>(a, d, bit0, out); break;
+    case 3: zeta_pass_kernel<3, OutT><<<grid, kZetaThreads, 0, st>>>(a, d, bit0, out); break;
+    case 4: zeta_pass_kernel<4, OutT><<<grid, kZetaThreads, 0, st>>>(a, d, bit0, out); break;
+    default: zeta_pass_kernel<5, OutT><<<grid, kZetaThreads, 0, st>>>(a, d, bit0, out); break;
   }
 }
 
@@ -495,7 +522,16 @@ fsi_status fsi_forest_values_mobius(fsi_forest_t F, const double* x_dev, int n_b
   fsi_status st = fsi_forest_mobius(F, x_dev, n_bg, bg_dev, work_dev, stream);
   if (st != FSI_OK) return st;
   const int d = F->d;
-  for (int bit0 = 0; bit0 < d; bit0 += kZetaBits) {
+  const int lb = std::min(d, kZetaLow);
+  if (lb == d) {
+    if (dtype == FSI_DTYPE_F32)
+      zeta_low_kernel<float><<<1, kThreads, 0, stream>>>(work_dev, lb, (float*)v_dev);
+    else
+      zeta_low_kernel<double><<<1, kThreads, 0, stream>>>(work_dev, lb, (double*)v_dev);
+  } else {
+    zeta_low_kernel<double><<<1 << (d - lb), kThreads, 0, stream>>>(work_dev, lb, work_dev);
+  }
+  for (int bit0 = lb; bit0 < d; bit0 += kZetaBits) {
     const int nb = std::min(kZetaBits, d - bit0);
     const bool last = bit0 + nb >= d;
     if (last && dtype == FSI_DTYPE_F32)
