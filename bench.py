@@ -226,6 +226,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--check-sample", type=int, default=4)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the single-instance d = 28 and d = 30 timings")
     ap.add_argument("--no-forest", action="store_true",
                     help="skip generating the tree games' value functions on the GPU")
     ap.add_argument("--no-indices", action="store_true",
@@ -348,6 +350,29 @@ def main():
     if not args.no_forest:
         vfun = bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads)
 
+    # ---- single instances beyond the register-phase kernel (d = 28, 30) ----
+    large = None
+    if not args.no_large:
+        large = {}
+        for dl, ll in ((28, 4), (30, 2)):
+            xl = torch.randn(1 << dl, dtype=torch.float32, device=dev)
+            pl = Plan(dl, ll, dtype="f32", precision=args.precision)
+            ol = pl.apply(xl)
+            torch.cuda.synchronize()
+            reps = max(1, args.steps // 4)
+            ev0.record(stream)
+            for _ in range(reps):
+                pl.apply(xl, ol)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            lms = ev0.elapsed_time(ev1) / reps
+            large[f"d{dl}_l{ll}"] = {"ms": lms, "values_per_s": (1 << dl) / (lms * 1e-3),
+                                     "hbm_frac": (1 << dl) * 4 / (lms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                     "tile_bits": pl.info()["tile_bits"]}
+            log(f"single instance d={dl} l={ll}: {lms:.2f} ms ({(1 << dl) / (lms * 1e-3):.3e} values/s)")
+            pl.close()
+            del xl, ol
+
     # ---- FP64 paths on the same instances ----
     fp64 = None
     errs = None
@@ -461,6 +486,7 @@ def main():
         "errors": errs,
         "indices": indices,
         "value_function": vfun,
+        "large_instances": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
