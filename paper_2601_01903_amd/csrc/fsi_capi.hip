@@ -75,6 +75,7 @@ struct fsi_batch_plan_s {
   double* Y = nullptr;
   void* work = nullptr;            // two-pass Moebius workspace
   double* partial = nullptr;       // register-phase kernel partial sums
+  double* wide_partial = nullptr;  // wide gather partial sums
   std::vector<FastClassHost> fclasses;
   std::vector<int> fast_of;        // per class: index into fclasses or -1
   LaunchArgs args{};
@@ -106,6 +107,7 @@ void free_batch(fsi_batch_plan_s* p) {
   if (p->Y) (void)hipFree(p->Y);
   if (p->work) (void)hipFree(p->work);
   if (p->partial) (void)hipFree(p->partial);
+  if (p->wide_partial) (void)hipFree(p->wide_partial);
   delete p;
 }
 
@@ -203,7 +205,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       const int kern = sc.kernel >= 0 ? sc.kernel : opts.kernel;
       const bool want_fast = kern != FSI_KERNEL_GENERIC && algo == ALGO_FUSED &&
                              fast_supported(prec) && lh[i] <= kFastMaxL && dh[i] >= fb &&
-                             dh[i] - fb <= 12 &&
+                             dh[i] - fb <= fast_max_high_bits(lh[i]) &&
                              fast_output_slots(dh[i], lh[i]) >= 0 &&
                              fast_output_slots(dh[i], lh[i]) <= kFastKmax &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
@@ -308,9 +310,41 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   }  std::vector<int2> red_chunks;
   int n_generic = 0;
   for (int i = 0; i < n; ++i) {
-    if (!insts[i].fast) { ++n_generic; continue; }
+    if (!insts[i].fast) {
+      // generic fused instances with many tiles: the wide gather
+      insts[i].wide = (algo == ALGO_FUSED && P->classes[P->cls_of[i]].h >= kWideMinH) ? 1 : 0;
+      if (!insts[i].wide) ++n_generic;
+      continue;
+    }
     const int Mi = P->classes[P->cls_of[i]].M;
     for (int k0 = 0; k0 < Mi; k0 += 64) red_chunks.push_back(make_int2(i, k0));
+  }
+  // wide gather items: per instance, output groups x tile ranges; the ranges
+  // (a power of two) give the machine about two items per CU
+  std::vector<WideItem> witems;
+  std::vector<WideGroup> wgroups;
+  int64_t wptot = 0;
+  {
+    int64_t total_groups = 0;
+    for (int i = 0; i < n; ++i)
+      if (insts[i].wide) total_groups += (P->classes[P->cls_of[i]].M + kWideOuts - 1) / kWideOuts;
+    int64_t nr_target = 1;
+    while (total_groups > 0 && nr_target * total_groups < 2 * (int64_t)n_cu) nr_target *= 2;
+    for (int i = 0; i < n; ++i) {
+      if (!insts[i].wide) continue;
+      const ClassHost& C = P->classes[P->cls_of[i]];
+      const int64_t ntile = (int64_t)1 << C.h;
+      const int64_t nr = std::min(nr_target, ntile);
+      const int64_t per = ntile / nr;
+      const int G = (C.M + kWideOuts - 1) / kWideOuts;
+      for (int g = 0; g < G; ++g) {
+        wgroups.push_back(WideGroup{i, g, (int32_t)nr, 0, wptot});
+        for (int64_t r = 0; r < nr; ++r)
+          witems.push_back(WideItem{i, g, (int32_t)(r * per), (int32_t)((r + 1) * per),
+                                    wptot + r * kWideOuts});
+        wptot += nr * kWideOuts;
+      }
+    }
   }
   // one launch per order l: items grouped by l (stable, so each group keeps
   // the instance order)
@@ -392,6 +426,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   const size_t o_fcls = stage(buf, fdev.data(), fdev.size());
   const size_t o_fitems = stage(buf, fitems.data(), fitems.size());
   const size_t o_red = stage(buf, red_chunks.data(), red_chunks.size());
+  const size_t o_witems = stage(buf, witems.data(), witems.size());
+  const size_t o_wgroups = stage(buf, wgroups.data(), wgroups.size());
   const size_t o_torder = stage(buf, torder.data(), torder.size());
   const size_t o_cls = stage(buf, cdev.data(), cdev.size());
   const size_t o_inst = stage(buf, insts.data(), insts.size());
@@ -425,7 +461,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     FastClassDev& D = fdev[f];
-    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk;
+    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk; D.mshift = F.mshift;
     fast_lds[F.l] = fast_lds_bytes(prec, F.l);
     fast_lds_max = std::max(fast_lds_max, fast_lds[F.l]);
     D.lam = reinterpret_cast<const double*>(A + fo[f].lam);
@@ -458,6 +494,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   if (ptot > 0) {
     e = hipMalloc(reinterpret_cast<void**>(&P->partial), ptot * sizeof(double));
     if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(partial) failed"); }
+  }
+  if (wptot > 0) {
+    e = hipMalloc(reinterpret_cast<void**>(&P->wide_partial), wptot * sizeof(double));
+    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(wide partial) failed"); }
   }
 
   // ---- schedule ----
@@ -498,6 +538,13 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.mob_lds = mob_lds;
   a.partial = P->partial;
   a.n_generic = n_generic;
+  a.wide_items = reinterpret_cast<const WideItem*>(A + o_witems);
+  a.n_wide_items = (int)witems.size();
+  a.grid_wide = std::max(1, std::min<int>((int)witems.size(), n_cu * 4));
+  a.wide_groups = reinterpret_cast<const WideGroup*>(A + o_wgroups);
+  a.n_wide_groups = (int)wgroups.size();
+  a.grid_wide_groups = std::max(1, std::min<int>((int)wgroups.size() * (kWideOuts / 256), n_cu * 4));
+  a.wide_partial = P->wide_partial;
   a.red_chunks = reinterpret_cast<const int2*>(A + o_red);
   a.n_red_chunks = (int)red_chunks.size();
   a.grid_red_chunks = std::max(1, std::min<int>((int)red_chunks.size(), n_cu * 8));

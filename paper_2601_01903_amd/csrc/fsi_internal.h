@@ -44,16 +44,16 @@ struct ClassDev {
 struct FastClassDev {
   int32_t d, l, h, M;
   int32_t nkk;                // slots per thread in use
-  int32_t pad;
+  int32_t mshift;             // bits of the Y byte offset in a metadata word
   const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
-  const uint32_t* meta;       // [256 * kFastMetaStride] per thread: Y byte offset | S_H << 16
+  const uint32_t* meta;       // [256 * kFastMetaStride] per thread: Y byte offset | S_H << mshift
   const uint32_t* gs8;        // [kFastMetaStride] byte stride between j-variants per slot
   const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
   const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
 };
 
 struct FastClassHost {
-  int d = 0, l = 0, h = 0, M = 0, nkk = 0;
+  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16;
   std::vector<double> lam;
   std::vector<uint32_t> meta, gs8;
   std::vector<int32_t> unit_mask, zrow;
@@ -73,7 +73,7 @@ struct InstDev {
   int32_t fcls;      // index into the register-phase class array
   int64_t pbase;     // first partial sum (doubles)
   int32_t pstride;   // partial sums per work item
-  int32_t pad2;
+  int32_t wide;      // 1: generic instance reduced by the wide gather
   const int32_t* pidx;  // [M] position of canonical output k in an item's partial sums
 };
 
@@ -102,6 +102,8 @@ int64_t sweep_peak_entries(int b, int l);
 std::string build_class(int d, int l, int b, int algo, int index, ClassHost* out);
 // Output slots per thread the register-phase kernel needs for (d, l), or -1.
 int fast_output_slots(int d, int l);
+// Most high bits (d - 11) the register-phase kernel's output metadata holds at order l.
+int fast_max_high_bits(int l);
 // Builds the register-phase kernel tables from an already built fused class
 // with b = 11 and l <= 4 (its final weights and output order).
 std::string build_fast_class(const ClassHost& C, FastClassHost* out);

@@ -58,6 +58,23 @@ bool fast_supported(int prec);
 size_t fast_lds_bytes(int prec, int l);
 int fast_wgs_per_cu(int prec, int l);
 
+// Wide gather (generic fused instances with many tiles): a work item is a
+// range of tiles and a group of up to kWideOuts outputs; each thread keeps
+// kWideK output accumulators in registers across the range. The partial
+// sums of a group's ranges are then added in range order.
+constexpr int kWideK = 16;
+constexpr int kWideOuts = 256 * kWideK;
+constexpr int kWideMinH = 10;      // instances with at least 2^10 tiles
+
+struct WideItem {
+  int32_t inst, group, t0, t1;     // outputs [group * kWideOuts, ...), tiles [t0, t1)
+  int64_t pofs;                    // its kWideOuts partial sums
+};
+struct WideGroup {
+  int32_t inst, group, nr, pad;    // nr ranges, partial sums at pofs + r * kWideOuts
+  int64_t pofs;
+};
+
 struct LaunchArgs {
   int prec, algo;
   const ClassDev* classes;
@@ -80,7 +97,12 @@ struct LaunchArgs {
   size_t tile_lds, mob_lds;
   const double* partial;      // register-phase kernel partial sums
   FastLaunch fast;            // n_items == 0: no register-phase stage
-  int n_generic;              // instances of the generic (or two-pass) path
+  int n_generic;              // instances of the generic (or two-pass) path outside the wide gather
+  const WideItem* wide_items;
+  int n_wide_items, grid_wide;
+  const WideGroup* wide_groups;
+  int n_wide_groups, grid_wide_groups;
+  double* wide_partial;
   const int2* red_chunks;     // (instance, first output) per 64 outputs of fast instances
   int n_red_chunks, grid_red_chunks;
 };

@@ -190,7 +190,7 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
     }
     const InstDev I = insts[lo];
     const int k = (int)(g - out_offset[lo]);
-    if (I.fast) continue;   // written by fast_reduce_kernel
+    if (I.fast || I.wide) continue;   // written by fast_reduce_kernel / wide_final_kernel
     const ClassDev* C = classes + I.cls;
     const uint32_t oi = C->oinfo[k];
     const uint32_t SH = C->osh[k];
@@ -213,6 +213,66 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
       }
     }
     out[I.ooff + k] = (OutT)acc;
+  }
+}
+
+// Wide gather: thread t of a work item owns outputs group * kWideOuts + t +
+// 256 q (q < kWideK) and adds, for every tile U of the item's range, the
+// per-tile result its output selects (slot |S_H & U| of its s_H block).
+// Outputs past M read entry 0 of the tile (in range) and are never stored
+// by the final pass.
+__global__ void __launch_bounds__(256)
+wide_gather_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
+                   const WideItem* __restrict__ items, int n_items,
+                   const int64_t* __restrict__ out_offset, const double* __restrict__ Y,
+                   double* __restrict__ partial) {
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const WideItem w = items[it];
+    const InstDev I = insts[w.inst];
+    const ClassDev* C = classes + I.cls;
+    const int M = (int)(out_offset[w.inst + 1] - out_offset[w.inst]);
+    const int64_t Ys = C->Ysize;
+    uint32_t yo[kWideK], sh[kWideK];
+    double acc[kWideK];
+#pragma unroll
+    for (int q = 0; q < kWideK; ++q) {
+      const int k = w.group * kWideOuts + q * 256 + (int)threadIdx.x;
+      const uint32_t oi = k < M ? C->oinfo[k] : 0u;
+      const uint32_t sH = oi >> 24;
+      yo[q] = (oi & 0xFFFFFFu) + sH * (sH + 1) / 2;
+      sh[q] = k < M ? C->osh[k] : 0u;
+      acc[q] = 0.0;
+    }
+    const double* __restrict__ Yb = Y + I.yoff;
+    for (int U = w.t0; U < w.t1; ++U) {
+      const double* __restrict__ Yt = Yb + (int64_t)U * Ys;
+#pragma unroll
+      for (int q = 0; q < kWideK; ++q) acc[q] += Yt[yo[q] + __popc(sh[q] & (uint32_t)U)];
+    }
+    double* P = partial + w.pofs;
+#pragma unroll
+    for (int q = 0; q < kWideK; ++q) P[q * 256 + threadIdx.x] = acc[q];
+  }
+}
+
+template <typename OutT>
+__global__ void __launch_bounds__(256)
+wide_final_kernel(const WideGroup* __restrict__ groups, int n_groups,
+                  const InstDev* __restrict__ insts, const int64_t* __restrict__ out_offset,
+                  const double* __restrict__ partial, OutT* __restrict__ out) {
+  // a workgroup takes 256 consecutive outputs of one group
+  constexpr int kChunks = kWideOuts / 256;
+  for (int ci = blockIdx.x; ci < n_groups * kChunks; ci += gridDim.x) {
+    const WideGroup G = groups[ci / kChunks];
+    const InstDev I = insts[G.inst];
+    const int M = (int)(out_offset[G.inst + 1] - out_offset[G.inst]);
+    const int j = (ci % kChunks) * 256 + (int)threadIdx.x;
+    const int k = G.group * kWideOuts + j;
+    if (k < M) {
+      double acc = 0.0;
+      for (int r = 0; r < G.nr; ++r) acc += partial[G.pofs + (int64_t)r * kWideOuts + j];
+      out[I.ooff + k] = (OutT)acc;
+    }
   }
 }
 
@@ -366,11 +426,11 @@ hipError_t configure_kernels(int prec, int algo, size_t tile_lds, size_t mob_lds
 
 int num_stages(const LaunchArgs& a) {
   // fused: [register-phase kernel per order l], [generic tile kernel],
-  //        [generic reduce], [register-phase reduce]
+  //        [generic reduce], [wide gather, wide final], [register-phase reduce]
   // two-pass: Moebius low pass, high passes, tile, reduce
   if (a.algo == ALGO_FUSED)
     return fast_groups(a.fast, nullptr) + (a.n_tile_items > 0) + (a.n_generic > 0) +
-           (a.n_red_chunks > 0);
+           2 * (a.n_wide_items > 0) + (a.n_red_chunks > 0);
   return 3 + a.n_mob_passes;
 }
 
@@ -384,8 +444,25 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
                        static_cast<InT*>(a.out));
     return hipGetLastError();
   }
-  if (a.algo != ALGO_FUSED ? stage == last
-                           : (a.n_generic > 0 && stage == last - (a.n_red_chunks > 0))) {
+  if (a.algo == ALGO_FUSED && a.n_wide_items > 0) {
+    const int wfin = last - (a.n_red_chunks > 0);
+    if (stage == wfin - 1) {
+      hipLaunchKernelGGL(wide_gather_kernel, dim3(a.grid_wide), dim3(256), 0, st, a.classes,
+                         a.insts, a.wide_items, a.n_wide_items, a.out_offset, a.Y,
+                         a.wide_partial);
+      return hipGetLastError();
+    }
+    if (stage == wfin) {
+      hipLaunchKernelGGL(wide_final_kernel<InT>, dim3(a.grid_wide_groups), dim3(256), 0, st,
+                         a.wide_groups, a.n_wide_groups, a.insts, a.out_offset, a.wide_partial,
+                         static_cast<InT*>(a.out));
+      return hipGetLastError();
+    }
+  }
+  if (a.algo != ALGO_FUSED
+          ? stage == last
+          : (a.n_generic > 0 &&
+             stage == last - (a.n_red_chunks > 0) - 2 * (a.n_wide_items > 0))) {
     hipLaunchKernelGGL(reduce_kernel<InT>, dim3(a.grid_reduce), dim3(256), 0, st, a.classes,
                        a.insts, a.n_inst, a.out_offset, a.total_out, a.Y, a.partial,
                        static_cast<InT*>(a.out));

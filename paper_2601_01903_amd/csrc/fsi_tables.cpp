@@ -265,6 +265,10 @@ std::string build_class(int d, int l, int b, int algo, int index, ClassHost* C) 
   return "";
 }
 
+int fast_max_high_bits(int l) {
+  return (l >= 1 && l <= t11::PA) ? 32 - t11::meta_shift(l) : 0;
+}
+
 int fast_output_slots(int d, int l) {
   if (d < t11::B || l > 4 || l > d) return -1;
   const int h = d - t11::B;
@@ -283,7 +287,8 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
   if (b != B) return "register-phase kernel needs 11-bit tiles";
   if (C.algo != ALGO_FUSED) return "register-phase kernel needs the fused algorithm";
   if (l > 4) return "register-phase kernel needs l <= 4";
-  if (h > kMaxH) return "too many high bits for the register-phase kernel";
+  F->mshift = meta_shift(l);
+  if (h > 32 - F->mshift) return "too many high bits for the register-phase kernel";
   F->d = C.d; F->l = l; F->h = h; F->M = C.M;
   // phase-C units and their maps
   const int nu = n3(l);
@@ -338,8 +343,9 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
       const int sH = popc(SH);
       const uint32_t A = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) + rank_colex(SL));
       const int kk = kb + (int)(q / kFastThreads), t = (int)(q % kFastThreads);
-      if (A * 8 >= (1u << 16) || SH >= (1u << kMaxH)) return "output metadata overflow";
-      F->meta[(size_t)t * kFastMetaStride + kk] = (A * 8) | (SH << 16);
+      if (A * 8 >= (1u << F->mshift) || (uint64_t)SH >= (1ull << (32 - F->mshift)))
+        return "output metadata overflow";
+      F->meta[(size_t)t * kFastMetaStride + kk] = (A * 8) | (SH << F->mshift);
       F->pidx[ks[q]] = kk * kFastThreads + t;
     }
     kb += nslot;

@@ -148,8 +148,15 @@ constexpr int ntasks(int L) {
   for (int s = 2; s <= L; ++s) n += row_tasks(s);
   return n;
 }
-// output metadata word: byte offset of Y(S_L, s_H, j = 0) | S_H << 16
-constexpr int kMaxH = 12;
+// output metadata word: byte offset of Y(S_L, s_H, j = 0) | S_H << mshift,
+// mshift = the bits the largest Y byte offset of the order needs; S_H gets
+// the other 32 - mshift bits (19 high bits for l <= 3, 18 for l = 4)
+constexpr int meta_shift(int L) {
+  int s = 1;
+  while ((1 << s) <= ysize(L) * 8) ++s;
+  return s;
+}
+constexpr int kMaxH = 32 - meta_shift(3);
 
 }  // namespace t11
 }  // namespace fsi

@@ -387,6 +387,8 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const uint4* meta_g = reinterpret_cast<const uint4*>(C->meta + tid * kFastMetaStride);
   const cdptr_u gs8 = (cdptr_u)C->gs8;
   const int nkk = C->nkk;
+  const int mshift = C->mshift;
+  const uint32_t omask = (1u << mshift) - 1u;
   int u_prev = -1;
 
   const int64_t vbase = I.voff;
@@ -579,7 +581,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // ---- cross-tile sum: E_S += Y[S_L, s_H, |S_H & U_H|] ----
     // slot kk holds outputs of one |S_L|: the j-stride gs8[kk] is uniform
     {
-      const uint32_t UHs = (uint32_t)UH << 16;
+      const uint32_t UHs = (uint32_t)UH << mshift;
       const unsigned char* Yb = reinterpret_cast<const unsigned char*>(Y);
       constexpr int GB = 9;   // outputs per batch of reads
 #pragma unroll
@@ -589,7 +591,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
         for (int q = 0; q < GB; ++q) {
           if (k0 + q < KMAX) {
             const uint32_t m = meta[k0 + q];
-            const uint32_t off = (m & 0xFFFFu) + (uint32_t)__popc(m & UHs) * gs8[k0 + q];
+            const uint32_t off = (m & omask) + (uint32_t)__popc(m & UHs) * gs8[k0 + q];
             v[q] = *reinterpret_cast<const double*>(Yb + off);
           }
         }

@@ -1,6 +1,6 @@
 """The operator at the largest sizes one MI355X holds in core (d = 26, 28, 30;
-the paper's own method stops near d = 25 for memory). FP32 storage, generic
-tile kernel (the register-phase kernel stops at d = 23).
+the paper's own method stops near d = 25 for memory). FP32 storage; l <= 3
+runs on the register-phase kernel, l = 4 beyond d = 20 on the generic one.
 
 d = 26 and 28: sampled outputs against the C oracle, which evaluates only the
 requested outputs (its Moebius transform still covers all 2^d values).
@@ -32,6 +32,8 @@ def integer_planted(d, n_terms, kmax, seed):
 def run(d, l, v32, precision="f32_compensated"):
     from paper_2601_01903_amd import fsi
     plan = fsi.Plan(d, l, dtype="f32", precision=precision)
+    # l <= 3 runs on the register-phase kernel at every d, l = 4 on the generic one
+    assert plan.schedule()["fast_instances"] == (1 if l <= 3 else 0)
     out = plan.apply(torch.from_numpy(v32).to(DEV))
     torch.cuda.synchronize()
     res = out.double().cpu().numpy()
@@ -81,3 +83,44 @@ def test_d30_planted_closed_form():
     assert normwise(got, want) < 1e-6
     assert abs(got[0]) == 0.0                          # v(empty) = 0 for a planted game
     assert abs(got.sum() - g.coefs.sum()) < 1e-4 * max(1.0, np.abs(got).max())
+
+
+@pytest.mark.parametrize("d,l,tb,dtype,prec", [(18, 3, 8, "f64", "f64"),
+                                               (16, 4, 6, "f32", "f32_compensated"),
+                                               (22, 4, 0, "f32", "f32_compensated")])
+def test_wide_gather_matches_oracle(d, l, tb, dtype, prec):
+    """Generic instances with at least 2^10 tiles sum their per-tile results
+    with the wide gather (tile ranges x output groups); every output against
+    the oracle, and two applies bitwise equal."""
+    from paper_2601_01903_amd import fsi
+    say(f"[case] wide gather d={d} l={l} tile_bits={tb} {prec}")
+    g = games.tree_game(d, 60, 5, games.rng_for(931, d))
+    v = games.tree_values(g)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    vin = v if dtype == "f64" else v.astype(np.float32).astype(np.float64)
+    plan = fsi.Plan(d, l, dtype=dtype, precision=prec, kernel="generic", tile_bits=tb)
+    assert d - plan.info()["tile_bits"] >= 10
+    x = torch.as_tensor(vin, dtype=tdt).to(DEV)
+    o1 = plan.apply(x).double().cpu().numpy()
+    o2 = plan.apply(x).double().cpu().numpy()
+    torch.cuda.synchronize()
+    plan.close()
+    assert np.array_equal(o1, o2)
+    ref = oracle.fsi_c(vin, d, l, nthreads=16)
+    assert normwise(o1, ref) < (1e-12 if dtype == "f64" else 1e-6)
+
+
+def test_wide_gather_in_a_mixed_batch():
+    from paper_2601_01903_amd import fsi
+    ds, ls = [20, 22, 12, 19], [4, 4, 2, 1]
+    say(f"[case] mixed batch with a wide instance {list(zip(ds, ls))}")
+    vals = [games.tree_values(games.tree_game(d, 40, 5, games.rng_for(932, i))).astype(np.float32)
+            for i, d in enumerate(ds)]
+    bp = fsi.BatchPlan(ds, ls, dtype="f32")
+    out = bp.apply(torch.from_numpy(np.concatenate(vals)).to(DEV), graph=True)
+    torch.cuda.synchronize()
+    o = out.double().cpu().numpy()
+    for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
+        ref = oracle.fsi_c(v.astype(np.float64), d, l, nthreads=16)
+        assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], ref) < 1e-6, (i, d, l)
+    bp.close()

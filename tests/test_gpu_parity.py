@@ -147,6 +147,22 @@ def test_register_kernel_wide_high_part(d, l):
     assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=16)) < 1e-12
 
 
+@pytest.mark.parametrize("d,l", [(24, 2), (25, 1)])
+def test_register_kernel_beyond_twelve_high_bits(d, l):
+    """The register-phase kernel at l <= 3 holds up to 19 high bits (the
+    output metadata word packs the Y offset into the bits the order needs)."""
+    fsi = fsi_mod()
+    say(f"[case] register kernel d={d} l={l} ({d - 11} high bits)")
+    v = np.random.default_rng(5100 + d).integers(-3, 4, size=1 << d).astype(np.float64)
+    plan = fsi.Plan(d, l, kernel="register")
+    assert plan.schedule()["fast_instances"] == 1
+    out = plan.apply(torch.as_tensor(v).to(DEV))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    plan.close()
+    assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=16)) < 1e-12
+
+
 def _ragged_batch():
     ds, ls = games.ragged_specs(512)
     built = games.build_many(lambda i: games.ragged_instance(i, ds[i]), range(len(ds)), threads=16)
