@@ -412,7 +412,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
   std::vector<FastClassDev> fdev(P->fclasses.size());
-  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx; };
+  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm; };
   std::vector<FOffs> fo(P->fclasses.size());
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
@@ -422,6 +422,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     fo[f].pidx = stage(buf, F.pidx.data(), F.pidx.size());
     fo[f].unit_mask = stage(buf, F.unit_mask.data(), F.unit_mask.size());
     fo[f].zrow = stage(buf, F.zrow.data(), F.zrow.size());
+    fo[f].uperm = stage(buf, F.uperm.data(), F.uperm.size());
   }
   const size_t o_fcls = stage(buf, fdev.data(), fdev.size());
   const size_t o_fitems = stage(buf, fitems.data(), fitems.size());
@@ -469,6 +470,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.gs8 = reinterpret_cast<const uint32_t*>(A + fo[f].gs8);
     D.unit_mask = reinterpret_cast<const int32_t*>(A + fo[f].unit_mask);
     D.zrow = reinterpret_cast<const int32_t*>(A + fo[f].zrow);
+    D.uperm = reinterpret_cast<const int32_t*>(A + fo[f].uperm);
   }
   if (fast_lds_max > 160 * 1024) {
     free_batch(P);

@@ -50,13 +50,14 @@ struct FastClassDev {
   const uint32_t* gs8;        // [kFastMetaStride] byte stride between j-variants per slot
   const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
   const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
+  const int32_t* uperm;       // [256] phase-C unit of thread t (units by |sigma_AB|)
 };
 
 struct FastClassHost {
   int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16;
   std::vector<double> lam;
   std::vector<uint32_t> meta, gs8;
-  std::vector<int32_t> unit_mask, zrow;
+  std::vector<int32_t> unit_mask, zrow, uperm;
   std::vector<int32_t> pidx;  // [M] slot index kk * 256 + t of canonical output k
 };
 

@@ -104,6 +104,29 @@ constexpr int unit_index(int L, int sa, int sb) {
 // element (i, unit, c) at ((2 i + c / 4) * n3 + unit) * 4 + c % 4
 constexpr int s2_elems(int L) { return (KAB + 1) * n3(L) * NC; }
 
+// phase-C units in order of |sigma_AB| (stable): thread t of phase C takes
+// unit v[t], so a wave's units share a lower bound kmin[w] on |sigma_AB|
+// (L + 1 for a wave without units)
+struct UnitOrder { int v[NT]; int kmin[NT / 64]; };
+constexpr UnitOrder mk_unit_order(int L) {
+  UnitOrder o{};
+  int n = 0;
+  int pop[NT] = {};
+  for (int k = 0; k <= L; ++k)
+    for (int sb = 0; sb < NB; ++sb)
+      for (int r = 0; r < NA; ++r) {
+        const int sa = orderA(r);
+        if (cpop(sa) + cpop(sb) == k) {
+          o.v[n] = ubase(L, sb) + r;
+          pop[n] = k;
+          ++n;
+        }
+      }
+  for (int t = n; t < NT; ++t) o.v[t] = 0;
+  for (int w = 0; w < NT / 64; ++w) o.kmin[w] = 64 * w < n ? pop[64 * w] : L + 1;
+  return o;
+}
+
 // ---- Z rows ----
 constexpr int zbase(int s) {
   int o = 0;

@@ -193,15 +193,15 @@ struct EmitS2 {
 };
 
 // Phase C -> Z row of S_L = sigma_AB | sigma_C << 8 (12 entries, zero padded).
-template <typename SwT, int L>
+template <typename SwT, int L, int KMIN>
 struct EmitZ {
   SwT* Z;
   const int (&zr)[NC];   // Z row per sigma_C (dump row where |S_L| > L)
-  int sAB;
+  int sAB;               // >= KMIN for every unit of the wave
   template <int SIG, int LO, int RC>
   __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
     constexpr int sC = cpop(SIG);
-    if constexpr (sC <= L) {
+    if constexpr (sC <= L - KMIN) {
       if (sAB <= L - sC) {
         using V = typename Vec4<SwT>::type;
         constexpr int VN = Vec4<SwT>::n;
@@ -345,6 +345,46 @@ __device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, cons
   }
 }
 
+// Phase C of one wave: every unit of the wave has |sigma_AB| >= KMIN, so its
+// counter rows past KAB - KMIN are zero and its leaves with |sigma_C| >
+// L - KMIN are never written: both are dropped at compile time.
+template <int L> struct UO { static constexpr UnitOrder o = mk_unit_order(L); };
+
+template <int L, int KMIN, typename SwT>
+__device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[NC], int sAB,
+                                        int u3) {
+  if constexpr (KMIN <= L) {
+    using V = typename Vec4<SwT>::type;
+    constexpr int VN = Vec4<SwT>::n;
+    constexpr int N3 = K<L>::N3;
+    constexpr int NR = KAB + 1 - KMIN;
+    SwT X3[NR][NC];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      if (i > KAB - sAB) {   // past this unit's counters: zero, not read
+#pragma unroll
+        for (int c = 0; c < NC; ++c) X3[i][c] = SwT(0);
+        continue;
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const V* src = reinterpret_cast<const V*>(S2 + ((2 * i + h) * N3 + u3) * 4);
+#pragma unroll
+        for (int q = 0; q < 4 / VN; ++q) {
+          const V v = src[q];
+          if constexpr (VN == 4) {
+            X3[i][4 * h] = v.x; X3[i][4 * h + 1] = v.y; X3[i][4 * h + 2] = v.z; X3[i][4 * h + 3] = v.w;
+          } else {
+            X3[i][4 * h + 2 * q] = v.x; X3[i][4 * h + 2 * q + 1] = v.y;
+          }
+        }
+      }
+    }
+    EmitZ<SwT, L, KMIN> ez{Z, zr, sAB};
+    rsweep<PC, 0, NR, 0>(X3, ez);
+  }
+}
+
 // ------------------------------------------------------------------ item
 template <int L, typename SwT, typename MobT, bool IN64>
 __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, const InstDev& I,
@@ -374,7 +414,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const int sA = __popc(sA_mask);
   const int wb = ((p2c >> 2) * N3 + p2r) * 4 + (p2c & 3);
   // phase C: thread = unit
-  const int u3 = tid < N3 ? tid : 0;
+  const int u3 = tid < N3 ? C->uperm[tid] : 0;
   const int sAB = __popc(C->unit_mask[u3]);
   int zr[NC];
 #pragma unroll
@@ -531,34 +571,15 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       }
     }
     __syncthreads();
-    // ---- phase C: thread per unit sigma_AB, counters relative to |sigma_AB| ----
+    // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|),
+    // counters relative to |sigma_AB| ----
     if (tid < N3) {
-      using V = typename Vec4<SwT>::type;
-      constexpr int VN = Vec4<SwT>::n;
-      SwT X3[KAB + 1][NC];
-#pragma unroll
-      for (int i = 0; i <= KAB; ++i) {
-        if (i > KAB - sAB) {   // past this unit's counters: zero, not read
-#pragma unroll
-          for (int c = 0; c < NC; ++c) X3[i][c] = SwT(0);
-          continue;
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const V* src = reinterpret_cast<const V*>(S2 + ((2 * i + h) * N3 + u3) * 4);
-#pragma unroll
-          for (int q = 0; q < 4 / VN; ++q) {
-            const V v = src[q];
-            if constexpr (VN == 4) {
-              X3[i][4 * h] = v.x; X3[i][4 * h + 1] = v.y; X3[i][4 * h + 2] = v.z; X3[i][4 * h + 3] = v.w;
-            } else {
-              X3[i][4 * h + 2 * q] = v.x; X3[i][4 * h + 2 * q + 1] = v.y;
-            }
-          }
-        }
+      switch (wave) {
+        case 0: phase_c<L, UO<L>::o.kmin[0], SwT>(S2, Z, zr, sAB, u3); break;
+        case 1: phase_c<L, UO<L>::o.kmin[1], SwT>(S2, Z, zr, sAB, u3); break;
+        case 2: phase_c<L, UO<L>::o.kmin[2], SwT>(S2, Z, zr, sAB, u3); break;
+        default: phase_c<L, UO<L>::o.kmin[3], SwT>(S2, Z, zr, sAB, u3); break;
       }
-      EmitZ<SwT, L> ez{Z, zr, sAB};
-      rsweep<PC, 0, KAB + 1, 0>(X3, ez);
     }
     // prefetch the next tile and this tile's output metadata while the
     // weight core runs
