@@ -174,14 +174,14 @@ struct EmitS1 {
 // counters i < RC (entries past this unit's range hold zeros), for the
 // prefixes with |sigma_A| + |sigma_B| <= L. Phase C reads only i <= 8 - |sigma_AB|,
 // all written here.
-template <typename SwT, int L>
+template <typename SwT, int L, int SAMIN>
 struct EmitS2 {
   SwT* S2;   // offset by ((c / 4) * n3 + rankA) * 4 + c % 4
-  int sA;
+  int sA;    // >= SAMIN
   template <int SIG, int LO, int RC>
   __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
     constexpr int sB = cpop(SIG);
-    if constexpr (sB <= L) {
+    if constexpr (sB <= L - SAMIN) {
       if (sA <= L - sB) {
         constexpr int UB = K<L>::ub.v[SIG];
         constexpr int N3 = K<L>::N3;
@@ -348,6 +348,59 @@ __device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, cons
 // Phase C of one wave: every unit of the wave has |sigma_AB| >= KMIN, so its
 // counter rows past KAB - KMIN are zero and its leaves with |sigma_C| >
 // L - KMIN are never written: both are dropped at compile time.
+// Phase B of one wave: every sigma_A of the wave has |sigma_A| >= SAMIN, so
+// its counter rows past PA - SAMIN are zero and its leaves with |sigma_B| >
+// L - SAMIN are never written. HALF 0 walks the sigma = 0 subtree of the
+// first output site (all 16 inputs), HALF 1 the sigma = 1 subtree (the 8
+// tau = 1 inputs).
+constexpr int kSAHi = cpop(orderA(8));   // |sigma_A| of rank 8
+template <int L, int SAMIN, int HALF, typename SwT>
+__device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r, int p2c) {
+  if constexpr (SAMIN <= L) {
+    if (sA > L) return;
+    using V = typename Vec4<SwT>::type;
+    constexpr int VN = Vec4<SwT>::n;
+    constexpr int H = NB / 2;
+    constexpr int R1 = row1_stride<SwT>();
+    constexpr int NRB = PA + 1 - SAMIN;
+    constexpr int W = HALF == 0 ? NB : H;       // inputs this half reads
+    EmitS2<SwT, L, SAMIN> e2{S2w, sA};
+    const SwT* src0 = S1 + p2r * R1 + NB * p2c + (HALF == 0 ? 0 : H);
+    SwT X[NRB][W];
+#pragma unroll
+    for (int r = 0; r < NRB; ++r) {
+      if (r <= PA - sA) {
+        const V* src = reinterpret_cast<const V*>(src0 + K<L>::off1v.v[r] * R1);
+#pragma unroll
+        for (int q = 0; q < W / VN; ++q) {
+          const V v = src[q];
+          if constexpr (VN == 4) {
+            X[r][4 * q] = v.x; X[r][4 * q + 1] = v.y; X[r][4 * q + 2] = v.z; X[r][4 * q + 3] = v.w;
+          } else {
+            X[r][2 * q] = v.x; X[r][2 * q + 1] = v.y;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int b = 0; b < W; ++b) X[r][b] = SwT(0);
+      }
+    }
+    if constexpr (HALF == 0) {
+      SwT Y0[NRB + 1][H];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        Y0[0][j] = X[0][j];
+#pragma unroll
+        for (int t = 1; t < NRB; ++t) Y0[t][j] = X[t][j] + X[t - 1][H + j];
+        Y0[NRB][j] = X[NRB - 1][H + j];
+      }
+      rsweep<PB - 1, 0, NRB + 1, 0>(Y0, e2);
+    } else {
+      rsweep<PB - 1, 1, NRB, H>(X, e2);
+    }
+  }
+}
+
 template <int L> struct UO { static constexpr UnitOrder o = mk_unit_order(L); };
 
 template <int L, int KMIN, typename SwT>
@@ -409,7 +462,8 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
 
   // ---- per-item thread constants ----
   // phase B: thread (half, rankA, c); half = tid / 128 is wave-uniform
-  const int p2half = tid >> 7, p2r = tid & 15, p2c = (tid >> 4) & 7;
+  // (waves 0, 2: sigma_A ranks 0-7; waves 1, 3: ranks 8-15)
+  const int p2r = (((tid & 127) >> 6) << 3) | (tid & 7), p2c = (tid >> 3) & 7;
   const int sA_mask = (int)((kOrderANibbles >> (4 * p2r)) & 15u);
   const int sA = __popc(sA_mask);
   const int wb = ((p2c >> 2) * N3 + p2r) * 4 + (p2c & 3);
@@ -511,64 +565,13 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // ---- phase B: thread (half, sigma_A, c), counters relative to |sigma_A|;
     // the first output site (b bit 3) is split between the two halves of the
     // workgroup: half 0 walks the sigma = 0 subtree, half 1 the sigma = 1
-    // subtree (which needs only the tau = 1 inputs) ----
-    if (sA <= L) {
-      using V = typename Vec4<SwT>::type;
-      constexpr int VN = Vec4<SwT>::n;
-      constexpr int H = NB / 2;
-      EmitS2<SwT, L> e2{S2 + wb, sA};
-      const SwT* src0 = S1 + p2r * R1 + NB * p2c;
-      if (p2half == 0) {
-        SwT X2[PA + 1][NB];
-#pragma unroll
-        for (int r = 0; r <= PA; ++r) {
-          if (r <= PA - sA) {
-            const V* src = reinterpret_cast<const V*>(src0 + K<L>::off1v.v[r] * R1);
-#pragma unroll
-            for (int q = 0; q < NB / VN; ++q) {
-              const V v = src[q];
-              if constexpr (VN == 4) {
-                X2[r][4 * q] = v.x; X2[r][4 * q + 1] = v.y; X2[r][4 * q + 2] = v.z; X2[r][4 * q + 3] = v.w;
-              } else {
-                X2[r][2 * q] = v.x; X2[r][2 * q + 1] = v.y;
-              }
-            }
-          } else {
-#pragma unroll
-            for (int b = 0; b < NB; ++b) X2[r][b] = SwT(0);
-          }
-        }
-        SwT Y0[PA + 2][H];
-#pragma unroll
-        for (int j = 0; j < H; ++j) {
-          Y0[0][j] = X2[0][j];
-#pragma unroll
-          for (int t = 1; t <= PA; ++t) Y0[t][j] = X2[t][j] + X2[t - 1][H + j];
-          Y0[PA + 1][j] = X2[PA][H + j];
-        }
-        rsweep<PB - 1, 0, PA + 2, 0>(Y0, e2);
-      } else {
-        SwT X1[PA + 1][H];
-#pragma unroll
-        for (int r = 0; r <= PA; ++r) {
-          if (r <= PA - sA) {
-            const V* src = reinterpret_cast<const V*>(src0 + K<L>::off1v.v[r] * R1 + H);
-#pragma unroll
-            for (int q = 0; q < H / VN; ++q) {
-              const V v = src[q];
-              if constexpr (VN == 4) {
-                X1[r][4 * q] = v.x; X1[r][4 * q + 1] = v.y; X1[r][4 * q + 2] = v.z; X1[r][4 * q + 3] = v.w;
-              } else {
-                X1[r][2 * q] = v.x; X1[r][2 * q + 1] = v.y;
-              }
-            }
-          } else {
-#pragma unroll
-            for (int b = 0; b < H; ++b) X1[r][b] = SwT(0);
-          }
-        }
-        rsweep<PB - 1, 1, PA + 1, H>(X1, e2);
-      }
+    // subtree (which needs only the tau = 1 inputs); in each half the second
+    // wave holds the sigma_A with |sigma_A| >= 2 ----
+    switch (wave) {
+      case 0: phase_b<L, 0, 0, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
+      case 1: phase_b<L, kSAHi, 0, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
+      case 2: phase_b<L, 0, 1, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
+      default: phase_b<L, kSAHi, 1, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
     }
     __syncthreads();
     // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|),
