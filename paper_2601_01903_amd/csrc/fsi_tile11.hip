@@ -230,7 +230,11 @@ struct Lds {
       imax2(rows1(L) * row1_stride<SwT>() * (int)sizeof(SwT),
             (nzrows(L) + 1) * ZROW * (int)sizeof(SwT)));
   static constexpr int reg3 = align256(lamblock(L) * 8);   // weights of the current |U_H|
-  static constexpr int bytes = reg1 + reg2 + reg3;
+  // zeros, read in place of the counter rows past a prefix's range by the
+  // waves that run the general sweep code (their row loads then need no
+  // branch and issue back to back)
+  static constexpr int zeros = 128;
+  static constexpr int bytes = reg1 + reg2 + reg3 + zeros;
 };
 
 // ------------------------------------------------------------ weight core
@@ -355,7 +359,8 @@ __device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, cons
 // tau = 1 inputs).
 constexpr int kSAHi = cpop(orderA(8));   // |sigma_A| of rank 8
 template <int L, int SAMIN, int HALF, typename SwT>
-__device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r, int p2c) {
+__device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r, int p2c,
+                                        const SwT* zrow) {
   if constexpr (SAMIN <= L) {
     if (sA > L) return;
     using V = typename Vec4<SwT>::type;
@@ -405,7 +410,7 @@ template <int L> struct UO { static constexpr UnitOrder o = mk_unit_order(L); };
 
 template <int L, int KMIN, typename SwT>
 __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[NC], int sAB,
-                                        int u3) {
+                                        int u3, const SwT* zrow) {
   if constexpr (KMIN <= L) {
     using V = typename Vec4<SwT>::type;
     constexpr int VN = Vec4<SwT>::n;
@@ -414,14 +419,15 @@ __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[N
     SwT X3[NR][NC];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-      if (i > KAB - sAB) {   // past this unit's counters: zero, not read
+      if (KMIN > 0 && i > KAB - sAB) {   // past this unit's counters: zero, not read
 #pragma unroll
         for (int c = 0; c < NC; ++c) X3[i][c] = SwT(0);
         continue;
       }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const V* src = reinterpret_cast<const V*>(S2 + ((2 * i + h) * N3 + u3) * 4);
+        const V* src = reinterpret_cast<const V*>(
+            KMIN > 0 || i <= KAB - sAB ? S2 + ((2 * i + h) * N3 + u3) * 4 : zrow);
 #pragma unroll
         for (int q = 0; q < 4 / VN; ++q) {
           const V v = src[q];
@@ -456,6 +462,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   SwT* S1 = reinterpret_cast<SwT*>(smem + LD::reg1);
   SwT* Z = reinterpret_cast<SwT*>(smem + LD::reg1);
   double* lamL = reinterpret_cast<double*>(smem + LD::reg1 + LD::reg2);
+  const SwT* zrow = reinterpret_cast<const SwT*>(smem + LD::reg1 + LD::reg2 + LD::reg3);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -568,20 +575,20 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // subtree (which needs only the tau = 1 inputs); in each half the second
     // wave holds the sigma_A with |sigma_A| >= 2 ----
     switch (wave) {
-      case 0: phase_b<L, 0, 0, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
-      case 1: phase_b<L, kSAHi, 0, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
-      case 2: phase_b<L, 0, 1, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
-      default: phase_b<L, kSAHi, 1, SwT>(S1, S2 + wb, sA, p2r, p2c); break;
+      case 0: phase_b<L, 0, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      case 1: phase_b<L, kSAHi, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      case 2: phase_b<L, 0, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      default: phase_b<L, kSAHi, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
     }
     __syncthreads();
     // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|),
     // counters relative to |sigma_AB| ----
     if (tid < N3) {
       switch (wave) {
-        case 0: phase_c<L, UO<L>::o.kmin[0], SwT>(S2, Z, zr, sAB, u3); break;
-        case 1: phase_c<L, UO<L>::o.kmin[1], SwT>(S2, Z, zr, sAB, u3); break;
-        case 2: phase_c<L, UO<L>::o.kmin[2], SwT>(S2, Z, zr, sAB, u3); break;
-        default: phase_c<L, UO<L>::o.kmin[3], SwT>(S2, Z, zr, sAB, u3); break;
+        case 0: phase_c<L, UO<L>::o.kmin[0], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 1: phase_c<L, UO<L>::o.kmin[1], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 2: phase_c<L, UO<L>::o.kmin[2], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        default: phase_c<L, UO<L>::o.kmin[3], SwT>(S2, Z, zr, sAB, u3, zrow); break;
       }
     }
     // prefetch the next tile and this tile's output metadata while the
@@ -643,6 +650,12 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
               const float* __restrict__ vals32, const double* __restrict__ vals64,
               const int32_t* __restrict__ torder, double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
+  {
+    using LD = Lds<L, SwT, MobT>;
+    uint32_t* z = reinterpret_cast<uint32_t*>(smem + LD::reg1 + LD::reg2 + LD::reg3);
+    if (threadIdx.x < LD::zeros / 4) z[threadIdx.x] = 0u;
+    __syncthreads();
+  }
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
