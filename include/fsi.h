@@ -121,9 +121,10 @@ typedef struct {
 
 /* Tile kernel of the fused algorithm. The register-phase kernel (tiles of
  * 11 low bits) covers every storage dtype and precision except
- * F32_FP64REG, at l <= 3 for 11 <= d <= 30 and at l = 4 for 11 <= d <= 20
- * (its per-thread output slots and the high bits its output metadata holds
- * bound the rest); the generic LDS kernel covers every (d, l). AUTO picks
+ * F32_FP64REG, at l <= 3 for 11 <= d <= 30 and at l = 4 for 11 <= d <= 29
+ * (the high bits its output metadata holds bound the rest; past d = 20 at
+ * l = 4 the outputs are split into groups, each gathered by its own pass
+ * over the tiles); the generic LDS kernel covers every (d, l). AUTO picks
  * the register-phase kernel where it applies. */
 typedef enum {
   FSI_KERNEL_AUTO = 0,

@@ -207,7 +207,6 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
                              fast_supported(prec) && lh[i] <= kFastMaxL && dh[i] >= fb &&
                              dh[i] - fb <= fast_max_high_bits(lh[i]) &&
                              fast_output_slots(dh[i], lh[i]) >= 0 &&
-                             fast_output_slots(dh[i], lh[i]) <= kFastKmax &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
       if (kern == FSI_KERNEL_REGISTER && !want_fast) {
         free_batch(P);
@@ -275,9 +274,12 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     });
     torder.insert(torder.end(), ord.begin(), ord.end());
   }
+  // tiles the register-phase kernel walks (each output group walks them all)
   int64_t fast_tiles = 0;
-  for (int i = 0; i < n; ++i)
-    if (P->fast_of[P->cls_of[i]] >= 0) fast_tiles += (int64_t)1 << P->classes[P->cls_of[i]].h;
+  for (int i = 0; i < n; ++i) {
+    const int f = P->fast_of[P->cls_of[i]];
+    if (f >= 0) fast_tiles += ((int64_t)1 << P->classes[P->cls_of[i]].h) * P->fclasses[f].ngroups;
+  }
   // tiles per work item: the largest power of two that still gives every
   // workgroup slot of the machine at least one item
   int64_t chunk = 1;
@@ -289,6 +291,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     if (sc.chunk_shift > 0) chunk <<= sc.chunk_shift;
     if (sc.chunk_shift < 0) chunk = std::max<int64_t>(1, chunk >> -sc.chunk_shift);
   }
+  // work items: output group major, then tile ranges; the partial sums of
+  // item (g, r) of an instance start at pbase + (g * nitems + r) * pstride
   std::vector<FastItem> fitems;
   int64_t ptot = 0;
   for (int i = 0; i < n; ++i) {
@@ -303,9 +307,26 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     insts[i].pbase = ptot;
     insts[i].pstride = F.nkk * kFastThreads;
     insts[i].nitems = (int32_t)((ntile + cs - 1) / cs);
-    for (int64_t tb = 0; tb < ntile; tb += cs) {
-      fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min(ntile, tb + cs), 0, ptot});
-      ptot += (int64_t)F.nkk * kFastThreads;
+    for (int g = 0; g < F.ngroups; ++g)
+      for (int64_t tb = 0; tb < ntile; tb += cs) {
+        fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min(ntile, tb + cs), g, ptot});
+        ptot += (int64_t)F.nkk * kFastThreads;
+      }
+  }
+  // per class: position of each canonical output in an instance's partial
+  // sums (its group's first item plus its slot)
+  std::vector<std::vector<int32_t>> fpidx(P->fclasses.size());
+  for (size_t f = 0; f < P->fclasses.size(); ++f) {
+    const FastClassHost& F = P->fclasses[f];
+    const int64_t ntile = (int64_t)1 << F.h;
+    const int64_t cs = std::min<int64_t>(chunk, ntile);
+    const int64_t nr = (ntile + cs - 1) / cs;
+    const int64_t pstride = (int64_t)F.nkk * kFastThreads;
+    fpidx[f].resize(F.pidx.size());
+    for (size_t k = 0; k < F.pidx.size(); ++k) {
+      const int64_t pos = (int64_t)F.pgroup[k] * nr * pstride + F.pidx[k];
+      if (pos >= ((int64_t)1 << 31)) { free_batch(P); return fail(FSI_ERR_INTERNAL, "partial sums too large"); }
+      fpidx[f][k] = (int32_t)pos;
     }
   }  std::vector<int2> red_chunks;
   int n_generic = 0;
@@ -412,14 +433,15 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
   std::vector<FastClassDev> fdev(P->fclasses.size());
-  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm; };
+  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm, gnkk; };
   std::vector<FOffs> fo(P->fclasses.size());
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     fo[f].lam = stage(buf, F.lam.data(), F.lam.size());
     fo[f].meta = stage(buf, F.meta.data(), F.meta.size());
     fo[f].gs8 = stage(buf, F.gs8.data(), F.gs8.size());
-    fo[f].pidx = stage(buf, F.pidx.data(), F.pidx.size());
+    fo[f].pidx = stage(buf, fpidx[f].data(), fpidx[f].size());
+    fo[f].gnkk = stage(buf, F.gnkk.data(), F.gnkk.size());
     fo[f].unit_mask = stage(buf, F.unit_mask.data(), F.unit_mask.size());
     fo[f].zrow = stage(buf, F.zrow.data(), F.zrow.size());
     fo[f].uperm = stage(buf, F.uperm.data(), F.uperm.size());
@@ -471,6 +493,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.unit_mask = reinterpret_cast<const int32_t*>(A + fo[f].unit_mask);
     D.zrow = reinterpret_cast<const int32_t*>(A + fo[f].zrow);
     D.uperm = reinterpret_cast<const int32_t*>(A + fo[f].uperm);
+    D.gnkk = reinterpret_cast<const int32_t*>(A + fo[f].gnkk);
   }
   if (fast_lds_max > 160 * 1024) {
     free_batch(P);
@@ -562,6 +585,9 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     a.fast.torder = reinterpret_cast<const int32_t*>(A + o_torder);
     a.fast.partial = P->partial;
     for (int l = 0; l <= kFastMaxL + 1; ++l) a.fast.lbeg[l] = lbeg[l];
+    for (int l = 0; l <= kFastMaxL; ++l) a.fast.grouped[l] = 0;
+    for (const FastClassHost& F : P->fclasses)
+      if (F.ngroups > 1) a.fast.grouped[F.l] = 1;
     for (int l = 0; l <= kFastMaxL; ++l) {
       a.fast.lds[l] = fast_lds[l];
       const int nl = l >= 1 ? lbeg[l + 1] - lbeg[l] : 0;

@@ -43,22 +43,26 @@ struct ClassDev {
 // stride between the j-variants of its partial results is uniform.
 struct FastClassDev {
   int32_t d, l, h, M;
-  int32_t nkk;                // slots per thread in use
+  int32_t nkk;                // slots per thread in use (largest over the output groups)
   int32_t mshift;             // bits of the Y byte offset in a metadata word
   const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
-  const uint32_t* meta;       // [256 * kFastMetaStride] per thread: Y byte offset | S_H << mshift
-  const uint32_t* gs8;        // [kFastMetaStride] byte stride between j-variants per slot
+  const uint32_t* meta;       // [groups * 256 * kFastMetaStride] per group and thread:
+                              // Y byte offset | S_H << mshift
+  const uint32_t* gs8;        // [groups * kFastMetaStride] byte stride between j-variants per slot
+  const int32_t* gnkk;        // [groups] slots per thread in use in each output group
   const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
   const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
   const int32_t* uperm;       // [256] phase-C unit of thread t (units by |sigma_AB|)
 };
 
 struct FastClassHost {
-  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16;
+  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16, ngroups = 1;
   std::vector<double> lam;
   std::vector<uint32_t> meta, gs8;
+  std::vector<int32_t> gnkk;
   std::vector<int32_t> unit_mask, zrow, uperm;
-  std::vector<int32_t> pidx;  // [M] slot index kk * 256 + t of canonical output k
+  std::vector<int32_t> pidx;    // [M] slot index kk * 256 + t of canonical output k in its group
+  std::vector<int32_t> pgroup;  // [M] output group of canonical output k
 };
 
 struct InstDev {

@@ -27,7 +27,7 @@ constexpr int kFastTileBits = 11;
 constexpr int kFastMaxL = 4;
 
 struct FastItem {
-  int32_t inst, tb, te, pad;       // tiles [tb, te) of the instance's tile order
+  int32_t inst, tb, te, group;     // tiles [tb, te) of the instance's tile order; output group
   int64_t pofs;                    // partial sums of this item
 };
 
@@ -42,6 +42,7 @@ struct FastLaunch {
   int lbeg[kFastMaxL + 2];
   int grid[kFastMaxL + 1];
   size_t lds[kFastMaxL + 1];
+  int grouped[kFastMaxL + 1];     // 1: an instance of this order has several output groups
   const void* vals32;
   const void* vals64;
   const int32_t* torder;

@@ -330,34 +330,50 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
     }
   // outputs: slots grouped by |S_L| (descending), each output of a group
   // at (slot kb + q / 256, thread q % 256) for its q-th position in
-  // canonical order
+  // canonical order. A slot holds 256 outputs of one |S_L|; consecutive
+  // slots go to one output group until it has kFastKmax of them (each group
+  // is gathered by its own work items over every tile).
   const size_t M = C.out_masks.size();
   const uint32_t lowmask = (1u << b) - 1;
   std::vector<std::vector<uint32_t>> byl(l + 1);
   for (size_t k = 0; k < M; ++k) byl[popc(C.out_masks[k] & lowmask)].push_back((uint32_t)k);
-  F->meta.assign((size_t)kFastThreads * kFastMetaStride, 0u);
-  F->gs8.assign(kFastMetaStride, 0u);
+  const int total = fast_output_slots(C.d, l);
+  if (total < 0) return "register-phase kernel does not apply";
+  F->ngroups = (total + kFastKmax - 1) / kFastKmax;
+  // only order 4 has a grouped kernel instantiation
+  if (F->ngroups > 1 && l != kFastMaxL) return "output groups are only built for l = 4";
+  F->meta.assign((size_t)F->ngroups * kFastThreads * kFastMetaStride, 0u);
+  F->gs8.assign((size_t)F->ngroups * kFastMetaStride, 0u);
+  F->gnkk.assign(F->ngroups, 0);
   F->pidx.assign(M, -1);
-  int kb = 0;
+  F->pgroup.assign(M, -1);
+  int slot = 0;   // running slot over all groups
   for (int sL = l; sL >= 0; --sL) {
     const std::vector<uint32_t>& ks = byl[sL];
     const int nslot = (int)((ks.size() + kFastThreads - 1) / kFastThreads);
-    if (kb + nslot > kFastKmax) return "too many output slots for the register-phase kernel";
-    for (int q = 0; q < nslot; ++q) F->gs8[kb + q] = (uint32_t)cbinom(B, sL) * 8u;
+    for (int q = 0; q < nslot; ++q) {
+      const int g = (slot + q) / kFastKmax, kk = (slot + q) % kFastKmax;
+      F->gs8[(size_t)g * kFastMetaStride + kk] = (uint32_t)cbinom(B, sL) * 8u;
+      F->gnkk[g] = std::max(F->gnkk[g], kk + 1);
+    }
     for (size_t q = 0; q < ks.size(); ++q) {
       const uint32_t S = C.out_masks[ks[q]];
       const uint32_t SL = S & lowmask, SH = S >> b;
       const int sH = popc(SH);
       const uint32_t A = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) + rank_colex(SL));
-      const int kk = kb + (int)(q / kFastThreads), t = (int)(q % kFastThreads);
+      const int gs = slot + (int)(q / kFastThreads), t = (int)(q % kFastThreads);
+      const int g = gs / kFastKmax, kk = gs % kFastKmax;
       if (A * 8 >= (1u << F->mshift) || (uint64_t)SH >= (1ull << (32 - F->mshift)))
         return "output metadata overflow";
-      F->meta[(size_t)t * kFastMetaStride + kk] = (A * 8) | (SH << F->mshift);
+      F->meta[((size_t)g * kFastThreads + t) * kFastMetaStride + kk] = (A * 8) | (SH << F->mshift);
       F->pidx[ks[q]] = kk * kFastThreads + t;
+      F->pgroup[ks[q]] = g;
     }
-    kb += nslot;
+    slot += nslot;
   }
-  F->nkk = kb;
+  if (slot != total) return "output slot count mismatch";
+  F->nkk = 0;
+  for (int g = 0; g < F->ngroups; ++g) F->nkk = std::max(F->nkk, F->gnkk[g]);
   return "";
 }
 

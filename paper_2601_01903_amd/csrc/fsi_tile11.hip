@@ -445,7 +445,7 @@ __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[N
 }
 
 // ------------------------------------------------------------------ item
-template <int L, typename SwT, typename MobT, bool IN64>
+template <int L, typename SwT, typename MobT, bool IN64, bool GROUPED>
 __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, const InstDev& I,
                                          const FastItem& W, const float* __restrict__ vals32,
                                          const double* __restrict__ vals64,
@@ -485,9 +485,13 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   double acc[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
-  const uint4* meta_g = reinterpret_cast<const uint4*>(C->meta + tid * kFastMetaStride);
-  const cdptr_u gs8 = (cdptr_u)C->gs8;
-  const int nkk = C->nkk;
+  // output group of the item (instances whose outputs need more than
+  // kFastKmax slots per thread are gathered in several groups)
+  const int grp = GROUPED ? __builtin_amdgcn_readfirstlane(W.group) : 0;
+  const uint4* meta_g =
+      reinterpret_cast<const uint4*>(C->meta + ((size_t)grp * NT + tid) * kFastMetaStride);
+  const cdptr_u gs8 = (cdptr_u)(C->gs8 + grp * kFastMetaStride);
+  const int nkk = GROUPED ? C->gnkk[grp] : C->nkk;
   const int mshift = C->mshift;
   const uint32_t omask = (1u << mshift) - 1u;
   int u_prev = -1;
@@ -643,7 +647,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
 // One kernel per order l (the items of a launch all have that order).
 // FP32 sweep: two workgroups per CU (2 waves per SIMD), so at most 256 VGPRs
 // per thread; the FP64 sweep's LDS allows one workgroup per CU.
-template <int L, typename SwT, typename MobT, bool IN64, int WPE>
+template <int L, typename SwT, typename MobT, bool IN64, int WPE, bool GROUPED>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               const FastItem* __restrict__ items, int n_items,
@@ -659,7 +663,8 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
-    run_item<L, SwT, MobT, IN64>(classes + I.fcls, I, W, vals32, vals64, torder, partial, smem);
+    run_item<L, SwT, MobT, IN64, GROUPED>(classes + I.fcls, I, W, vals32, vals64, torder, partial,
+                                          smem);
     __syncthreads();
   }
 }
@@ -677,11 +682,16 @@ constexpr int lds_bytes_for(int L) {
 // ------------------------------------------------------------------ launcher
 template <typename SwT> constexpr int wpe_for() { return sizeof(SwT) == 4 ? 2 : 1; }
 
+// Output groups occur only at l = 4 (lower orders need at most 20 slots
+// per thread), so only that order has a grouped instantiation; a launch
+// uses it when one of its instances has more than one group.
 template <int L, typename SwT, typename MobT, bool IN64>
 static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
   const int ib = f.lbeg[L], n = f.lbeg[L + 1] - f.lbeg[L];
   if (n <= 0) return hipSuccess;
-  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>()>;
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false>;
+  if constexpr (L == kFastMaxL)
+    if (f.grouped[L]) k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true>;
   hipLaunchKernelGGL(k, dim3(f.grid[L]), dim3(t11::NT), f.lds[L], st, f.classes, f.insts,
                      f.items + ib, n, static_cast<const float*>(f.vals32),
                      static_cast<const double*>(f.vals64), f.torder, f.partial);
@@ -690,9 +700,16 @@ static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
 
 template <int L, typename SwT, typename MobT, bool IN64>
 static hipError_t config_t11(size_t lds) {
-  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>()>;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if constexpr (L == kFastMaxL) {
+    if (e != hipSuccess) return e;
+    auto kg = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true>;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kg),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  }
+  return e;
 }
 
 template <typename SwT, typename MobT, bool IN64>

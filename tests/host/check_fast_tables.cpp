@@ -50,7 +50,7 @@ int main() {
   for (int l = 1; l <= 4; ++l)
     for (int d = 11; d <= 30; ++d) {
       const int slots = fast_output_slots(d, l);
-      const bool eligible = slots >= 0 && slots <= kFastKmax && d - 11 <= fast_max_high_bits(l);
+      const bool eligible = slots >= 0 && d - 11 <= fast_max_high_bits(l);
       if (!eligible) continue;
       ClassHost C;
       FastClassHost F;
@@ -60,15 +60,25 @@ int main() {
       e = build_fast_class(C, &F);
       CHECK(e.empty(), "d=%d l=%d build_fast_class: %s", d, l, e.c_str());
       if (!e.empty()) continue;
-      CHECK(F.nkk == slots, "d=%d l=%d nkk %d != slots %d", d, l, F.nkk, slots);
+      CHECK(F.ngroups == (slots + kFastKmax - 1) / kFastKmax, "d=%d l=%d: %d output groups", d, l,
+            F.ngroups);
+      int sum = 0;
+      for (int g = 0; g < F.ngroups; ++g) {
+        CHECK(F.gnkk[g] >= 1 && F.gnkk[g] <= kFastKmax, "d=%d l=%d group %d: %d slots", d, l, g,
+              F.gnkk[g]);
+        sum += F.gnkk[g];
+      }
+      CHECK(sum == slots, "d=%d l=%d: %d slots over the groups, %d needed", d, l, sum, slots);
       const uint32_t omask = (1u << F.mshift) - 1u;
       std::set<int> used;
       for (size_t k = 0; k < C.out_masks.size(); ++k) {
-        const int p = F.pidx[k];
-        CHECK(p >= 0 && p < F.nkk * kFastThreads, "d=%d l=%d output %zu: slot out of range", d, l, k);
-        CHECK(used.insert(p).second, "d=%d l=%d: slot used twice", d, l);
+        const int p = F.pidx[k], g = F.pgroup[k];
+        CHECK(g >= 0 && g < F.ngroups, "d=%d l=%d output %zu: group out of range", d, l, k);
+        if (g < 0 || g >= F.ngroups) continue;
+        CHECK(p >= 0 && p < F.gnkk[g] * kFastThreads, "d=%d l=%d output %zu: slot out of range", d, l, k);
+        CHECK(used.insert(g * kFastKmax * kFastThreads + p).second, "d=%d l=%d: slot used twice", d, l);
         const int kk = p / kFastThreads, t = p % kFastThreads;
-        const uint32_t m = F.meta[(size_t)t * kFastMetaStride + kk];
+        const uint32_t m = F.meta[((size_t)g * kFastThreads + t) * kFastMetaStride + kk];
         const uint32_t S = C.out_masks[k];
         const uint32_t SL = S & 0x7FFu, SH = S >> 11;
         CHECK((m >> F.mshift) == SH, "d=%d l=%d output %zu: S_H decodes wrongly", d, l, k);
@@ -78,8 +88,9 @@ int main() {
         const uint32_t want = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) +
                                          rank_colex(SL)) * 8u;
         CHECK((m & omask) == want, "d=%d l=%d output %zu: Y offset decodes wrongly", d, l, k);
-        CHECK(F.gs8[kk] == (uint32_t)cbinom(B, sL) * 8u, "d=%d l=%d: j stride of slot %d", d, l, kk);
-        CHECK((m & omask) + (uint32_t)sH * F.gs8[kk] < (uint32_t)ysize(l) * 8u,
+        const uint32_t gs = F.gs8[(size_t)g * kFastMetaStride + kk];
+        CHECK(gs == (uint32_t)cbinom(B, sL) * 8u, "d=%d l=%d: j stride of slot %d", d, l, kk);
+        CHECK((m & omask) + (uint32_t)sH * gs < (uint32_t)ysize(l) * 8u,
               "d=%d l=%d output %zu: Y offset past the tile's results", d, l, k);
       }
       CHECK((int)F.lam.size() == (F.h + 1) * lamblock(l), "d=%d l=%d: weight block size", d, l);

@@ -1,6 +1,7 @@
 """The operator at the largest sizes one MI355X holds in core (d = 26, 28, 30;
-the paper's own method stops near d = 25 for memory). FP32 storage; l <= 3
-runs on the register-phase kernel, l = 4 beyond d = 20 on the generic one.
+the paper's own method stops near d = 25 for memory). FP32 storage, on the
+register-phase kernel (at l = 4 past d = 20 with its outputs split into
+groups, each gathered by its own pass over the tiles).
 
 d = 26 and 28: sampled outputs against the C oracle, which evaluates only the
 requested outputs (its Moebius transform still covers all 2^d values).
@@ -32,8 +33,8 @@ def integer_planted(d, n_terms, kmax, seed):
 def run(d, l, v32, precision="f32_compensated"):
     from paper_2601_01903_amd import fsi
     plan = fsi.Plan(d, l, dtype="f32", precision=precision)
-    # l <= 3 runs on the register-phase kernel at every d, l = 4 on the generic one
-    assert plan.schedule()["fast_instances"] == (1 if l <= 3 else 0)
+    # the register-phase kernel holds up to 25, 22, 20, 18 high bits at l = 1..4
+    assert plan.schedule()["fast_instances"] == (1 if d - 11 <= {1: 25, 2: 22, 3: 20, 4: 18}[l] else 0)
     out = plan.apply(torch.from_numpy(v32).to(DEV))
     torch.cuda.synchronize()
     res = out.double().cpu().numpy()
@@ -41,7 +42,7 @@ def run(d, l, v32, precision="f32_compensated"):
     return res
 
 
-@pytest.mark.parametrize("d,l,n_sample", [(26, 3, 20), (28, 2, 10)])
+@pytest.mark.parametrize("d,l,n_sample", [(26, 3, 20), (28, 2, 10), (28, 4, 12)])
 def test_large_d_sampled_outputs(d, l, n_sample):
     say(f"[case] large d={d} l={l} FP32 planted (integer coefficients)")
     g = integer_planted(d, 30, 5, d)
@@ -116,7 +117,7 @@ def test_wide_gather_in_a_mixed_batch():
     say(f"[case] mixed batch with a wide instance {list(zip(ds, ls))}")
     vals = [games.tree_values(games.tree_game(d, 40, 5, games.rng_for(932, i))).astype(np.float32)
             for i, d in enumerate(ds)]
-    bp = fsi.BatchPlan(ds, ls, dtype="f32")
+    bp = fsi.BatchPlan(ds, ls, dtype="f32", kernel="generic")
     out = bp.apply(torch.from_numpy(np.concatenate(vals)).to(DEV), graph=True)
     torch.cuda.synchronize()
     o = out.double().cpu().numpy()

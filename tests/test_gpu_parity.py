@@ -135,11 +135,11 @@ def test_register_kernel_fp64_exact(d, l, kernel):
     assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=8)) < 1e-12
 
 
-@pytest.mark.parametrize("d,l", [(21, 3), (22, 2), (23, 1), (22, 3), (21, 4)])
+@pytest.mark.parametrize("d,l", [(21, 3), (22, 2), (23, 1), (22, 3), (21, 4), (22, 4)])
 def test_register_kernel_wide_high_part(d, l):
-    """Up to 12 high bits (2^12 tiles per instance); d = 21, l = 4 needs more
-    output slots than the register-phase kernel holds and takes the generic
-    kernel (the plan must still succeed)."""
+    """Up to 12 high bits (2^12 tiles per instance); at l = 4 past d = 20 the
+    outputs need more slots than a thread holds and are split into output
+    groups, each gathered by its own work items."""
     say(f"[case] wide high part d={d} l={l}")
     v = np.random.default_rng(5000 + d * 7 + l).integers(-3, 4, size=1 << d).astype(np.float64)
     got, info = gpu_apply(v, d, l)
