@@ -111,3 +111,21 @@ def test_unknown_index_rejected():
     st = fsi.load().fsi_plan_ex(8, 2, ctypes.byref(o), ctypes.byref(h))
     assert st == 1  # FSI_ERR_INVALID_ARG
     assert h.value is None
+
+
+@pytest.mark.parametrize("index", ["ksii", "sii"])
+def test_index_grouped_register_kernel(index):
+    """d = 22, l = 4 runs the register-phase kernel with two output groups."""
+    fsi = fsi_mod()
+    d, l = 22, 4
+    say(f"[case] index={index} d={d} l={l} FP32, output groups")
+    g = games.tree_game(d, 60, 5, games.rng_for(505, 0))
+    v32 = games.tree_values(g).astype(np.float32)
+    plan = fsi.Plan(d, l, dtype="f32", index=index)
+    assert plan.schedule()["fast_instances"] == 1
+    out = plan.apply(torch.from_numpy(v32).to(DEV))
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    plan.close()
+    ref = oracle.fsi_c(v32.astype(np.float64), d, l, nthreads=16, index=index)
+    assert normwise(got, ref) < 1e-6
