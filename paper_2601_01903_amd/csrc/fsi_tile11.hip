@@ -2,7 +2,8 @@
 // 2^11 values, l <= 4.
 //
 // A workgroup of 256 threads owns a work item: a run of tiles of one
-// instance (raw v, high index U_H). Per tile it computes
+// instance (raw v, high index U_H) and one group of its outputs. Per tile it
+// computes
 //   - the in-tile Moebius butterfly (Sec. 3.2) over the 11 low bits: bits
 //     8-10 in registers straight from the coalesced loads, bits 4-7 and 0-3
 //     through two LDS transposes;
@@ -12,20 +13,26 @@
 //     phase's output bits depth first: each output state adds its tau = 0
 //     and tau = 1 predecessors (the sparse MPO cores). Between phases the
 //     (sigma, t) states go through LDS, truncated to |sigma| <= l (the
-//     compressed output prefix);
+//     compressed output prefix). In phases B and C the threads are ordered
+//     so that each wave's prefixes share a lower bound on their popcount, and
+//     each wave runs code compiled for that bound;
 //   - the final weight core with the Moebius cores of the high sites
 //     precontracted into it (Sec. 4.5 applied to the high sites), in FP64:
 //     Y[S_L, s_H, j] = sum_t lambda_u(s_L + s_H, t, s_H + u - j) Z[S_L, t],
-//     u = |U_H|, the weights read through the scalar cache;
-//   - the cross-tile sum E_S += Y[S_L, |S_H|, |S_H & U_H|] in FP64 registers.
+//     u = |U_H|, the weights of the current u staged in LDS and read at
+//     wave-uniform addresses;
+//   - the cross-tile sum E_S += Y[S_L, |S_H|, |S_H & U_H|] in FP64 registers
+//     for the outputs of the item's group.
 // At the end of the item the FP64 partial sums go to a workspace; the
 // reduction kernel adds the items of an instance in a fixed order.
 //
 // Every LDS layout is a compile-time function of l (fsi_tile11.h), so the
 // hot loops address LDS with one per-thread base register and immediate
-// offsets. LDS is used in two regions that alias across the phases:
+// offsets. LDS regions:
 //   region 1: raw-tile transposes -> phase-B states S2 -> partial results Y
 //   region 2: phase-A states S1 -> final states Z
+//   region 3: the final-core weights of the current |U_H|
+//   a zero row read in place of counter rows past a unit's range
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <type_traits>
