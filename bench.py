@@ -220,7 +220,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-inst", type=int, default=256)
-    ap.add_argument("--precision", default="f32_compensated")
+    ap.add_argument("--precision", default="f32_fp64mob",
+                    help="FP32-storage precision form of the timed region (the library's AUTO "
+                         "choice by default); the other forms are timed beside it")
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--tile-bits", type=int, default=0)
     ap.add_argument("--cpu-sample", type=int, default=128)
@@ -345,6 +347,28 @@ def main():
             bpi.close()
             log(f"index {index}: {ims:.3f} ms/step, oracle sample err {max(ierr):.2e}")
 
+    # ---- the other FP32-storage precision forms on the same workload ----
+    forms = {}
+    for form in ("f32_compensated", "f32", "f32_fp64mob"):
+        if form == args.precision:
+            continue
+        bpf = BatchPlan([d] * n, [l] * n, dtype="f32", precision=form, algo=args.algo,
+                        tile_bits=args.tile_bits, autotune=not args.no_autotune)
+        of = torch.empty_like(out32)
+        for _ in range(args.warmup):
+            bpf.apply(x32, of)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            bpf.apply(x32, of)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        fms = ev0.elapsed_time(ev1) / args.steps
+        forms[form] = {"ms_per_step": fms, "values_per_s": n * N / (fms * 1e-3),
+                       "out": of.double().cpu().numpy()}
+        bpf.close()
+        log(f"precision form {form}: {fms:.3f} ms/step")
+
     # ---- value functions of the tree-game half generated on the GPU ----
     vfun = None
     if not args.no_forest:
@@ -424,6 +448,11 @@ def main():
                 "vs_fp64_gpu_max_tree": float(np.max(per[0::2])),
                 "vs_fp64_gpu_max_planted": float(np.max(per[1::2]))}
         log(f"FP64 plain {plain_ms:.2f} ms/pass, batched {b64_ms:.3f} ms; FP32 err {errs}")
+        for form, rec_f in forms.items():
+            pf = [normwise(rec_f["out"][i * M:(i + 1) * M], res64[i * M:(i + 1) * M])
+                  for i in range(n)]
+            rec_f["vs_fp64_gpu_max"] = float(np.max(pf))
+            rec_f["vs_fp64_gpu_median"] = float(np.median(pf))
 
     # ---- CPU oracle: parity sample and baseline timing ----
     import oracle
@@ -484,6 +513,8 @@ def main():
         "speedup_vs_plain_fp64": (fp64["plain_ms_per_pass"] / ms_per_step) if fp64 else None,
         "speedup_vs_batched_fp64": (fp64["batched_ms_per_step"] / ms_per_step) if fp64 else None,
         "errors": errs,
+        "precision_forms": {k: {kk: vv for kk, vv in v.items() if kk != "out"}
+                            for k, v in forms.items()},
         "indices": indices,
         "value_function": vfun,
         "large_instances": large,

@@ -60,11 +60,13 @@ typedef enum {
   FSI_PREC_F64 = 0,             /* FP64 storage, FP64 everywhere            */
   FSI_PREC_F32 = 1,             /* FP32 Moebius, FP32 sweep accumulation    */
   FSI_PREC_F32_COMPENSATED = 2, /* two-float Moebius, FP32 sweep            */
-  FSI_PREC_F32_FP64MOB = 3,     /* FP64 Moebius (cancellation-heavy input), */
-                                /* FP32 sweep                               */
+  FSI_PREC_F32_FP64MOB = 3,     /* FP64 Moebius, FP32 sweep                 */
   FSI_PREC_F32_FP64REG = 4,     /* FP32 storage, FP64 Moebius and sweep     */
-  FSI_PREC_AUTO = 5             /* F64 for FP64 storage, F32_COMPENSATED    */
-                                /* for FP32 storage                         */
+  FSI_PREC_AUTO = 5             /* F64 for FP64 storage; F32_FP64MOB for    */
+                                /* FP32 storage (on gfx950 FP64 runs at     */
+                                /* half the FP32 rate, so the FP64          */
+                                /* butterfly is cheaper than the two-float  */
+                                /* one and at least as accurate)            */
 } fsi_precision;
 
 typedef enum {

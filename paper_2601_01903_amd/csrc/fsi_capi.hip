@@ -112,7 +112,7 @@ void free_batch(fsi_batch_plan_s* p) {
 }
 
 int resolve_prec(int dtype, int prec) {
-  if (prec == FSI_PREC_AUTO) return dtype == FSI_DTYPE_F64 ? PREC_F64 : PREC_F32_COMP;
+  if (prec == FSI_PREC_AUTO) return dtype == FSI_DTYPE_F64 ? PREC_F64 : PREC_F32_FP64MOB;
   return prec;
 }
 
