@@ -149,6 +149,39 @@ def bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads):
 
     mob_ms = timed(gen_mobius)
     chain_mob_ms = timed(gen_mobius, with_fsi=True)
+
+    # FSI of the 128 tree games straight from their Moebius coefficients
+    # (Moebius input: no subset sums, no in-tile butterfly) against the chain
+    # through v, both on a 128-instance plan
+    from paper_2601_01903_amd import BatchPlan
+    nt = len(tree_ids)
+    bp_v = BatchPlan([d] * nt, [4] * nt, dtype="f32", autotune=not args.no_autotune)
+    bp_a = BatchPlan([d] * nt, [4] * nt, dtype="f32", autotune=not args.no_autotune,
+                     input="mobius")
+    x128 = torch.empty(nt * N, dtype=torch.float32, device=dev)
+    o_v = torch.empty(bp_v.out_offset[-1], dtype=torch.float32, device=dev)
+    o_a = torch.empty_like(o_v)
+
+    def chain_v():
+        for k in range(nt):
+            forests[k].values(xs[k], bgs[k], dtype="f32", out=x128[k * N:(k + 1) * N],
+                              method="mobius", work=work)
+        bp_v.apply(x128, o_v)
+
+    def chain_a():
+        for k in range(nt):
+            forests[k].mobius(xs[k], bgs[k], out=work)
+            x128[k * N:(k + 1) * N].copy_(work)
+        bp_a.apply(x128, o_a)
+
+    chain_v128_ms = timed(chain_v)
+    chain_a128_ms = timed(chain_a)
+    ov, oa = o_v.double().cpu().numpy(), o_a.double().cpu().numpy()
+    M4 = bp_v.out_offset[1]
+    chain_diff = max(normwise(oa[k * M4:(k + 1) * M4], ov[k * M4:(k + 1) * M4]) for k in range(nt))
+    bp_v.close()
+    bp_a.close()
+    del x128, o_v, o_a
     got_m = xv.cpu().numpy()
     mob_err = max(float(np.max(np.abs(got_m[i * N:(i + 1) * N] - vals32[i * N:(i + 1) * N]))
                         / np.max(np.abs(vals32[i * N:(i + 1) * N]))) for i in tree_ids)
@@ -198,6 +231,12 @@ def bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads):
                             "coalitions_per_s": len(tree_ids) * N / (mob_ms * 1e-3),
                             "chain_ms_per_step": chain_mob_ms,
                             "max_rel_diff_vs_seeded_inputs": mob_err},
+           "fsi_of_128_tree_games": {
+               "via_values_ms": chain_v128_ms,
+               "via_moebius_input_ms": chain_a128_ms,
+               "max_normwise_diff": chain_diff,
+               "note": "Moebius route to v then FSI, against scattered Moebius coefficients "
+                       "then FSI with Moebius input"},
            "multi_background": {"n_bg": 100, "ms": bg_ms,
                                 "coalition_values_per_s": N / (bg_ms * 1e-3),
                                 "oracle_sample_exact": bool(exact_bg),
@@ -207,6 +246,8 @@ def bench_forest(args, n, d, N, vals32, x32, stream, bp32, out32, threads):
                           "sample": f"{len(samp)} coalitions of instance 0, single-coalition walk"}}
     log(f"value functions (Moebius route): {mob_ms:.3f} ms, chain {chain_mob_ms:.3f} ms, "
         f"max rel diff {mob_err:.2e}")
+    log(f"FSI of the 128 tree games: via v {chain_v128_ms:.3f} ms, via Moebius input "
+        f"{chain_a128_ms:.3f} ms, diff {chain_diff:.2e}")
     log(f"value functions: {gen_ms:.3f} ms for {len(tree_ids)} forests "
         f"({rec['coalitions_per_s']:.3e} coalitions/s), chain {chain_ms:.3f} ms, "
         f"100 backgrounds {bg_ms:.3f} ms (Moebius route {bg_mob_ms:.3f} ms), "

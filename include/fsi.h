@@ -108,6 +108,14 @@ typedef enum {
   FSI_INDEX_BII = 4
 } fsi_index;
 
+/* What the input buffer holds. FSI_INPUT_MOBIUS: the Moebius transform a
+ * of the value vector (a(S) = sum over subsets T of S of (-1)^|S - T| v(T),
+ * Sec. 2.2), so the plan applies only the correction of Eq. 3 - 4,
+ * I_S = sum_{T superset of S} W(s, |T|) a(T) (the MPO on a, Sec. 4.4; for
+ * callers that already hold Moebius coefficients, e.g. fsi_forest_mobius).
+ * Needs the fused algorithm (FSI_ALGO_AUTO or FSI_ALGO_FUSED). */
+typedef enum { FSI_INPUT_VALUES = 0, FSI_INPUT_MOBIUS = 1 } fsi_input;
+
 typedef struct {
   int32_t dtype;                 /* fsi_dtype, default FSI_DTYPE_F64         */
   int32_t precision;             /* fsi_precision, default FSI_PREC_AUTO     */
@@ -118,7 +126,8 @@ typedef struct {
                                  /* time (see fsi_schedule), keep the best   */
   int32_t kernel;                /* fsi_kernel, default FSI_KERNEL_AUTO      */
   int32_t index;                 /* fsi_index, default FSI_INDEX_FSI         */
-  int32_t reserved[2];           /* must be 0                                */
+  int32_t input;                 /* fsi_input, default FSI_INPUT_VALUES      */
+  int32_t reserved[1];           /* must be 0                                */
 } fsi_plan_opts;
 
 /* Tile kernel of the fused algorithm. The register-phase kernel (tiles of

@@ -17,6 +17,7 @@ from .fsi_oracle import (  # noqa: F401
     index_weight_exact,
     index_weight_table_f64,
     interaction,
+    interaction_from_mobius,
     fsi,
     fsi_batch,
     mobius,
@@ -58,6 +59,9 @@ def _load():
         lib.oracle_fsi.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, ip,
                                    ctypes.c_int64, dp, ctypes.c_int]
         lib.oracle_fsi.restype = ctypes.c_int
+        lib.oracle_superset_sums.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, ip,
+                                             ctypes.c_int64, dp, ctypes.c_int]
+        lib.oracle_superset_sums.restype = None
         lib.oracle_mobius.argtypes = [dp, ctypes.c_int]
         lib.oracle_mobius.restype = None
         lib.oracle_ranked_sums_int.argtypes = [ip, ctypes.c_int, ip, ctypes.c_int64,
@@ -87,6 +91,27 @@ def fsi_c(v, d: int, l: int, nthreads: int = 1, index: str = "fsi") -> np.ndarra
                         E.ctypes.data_as(dp), int(nthreads))
     if rc != 0:
         raise MemoryError("oracle_fsi: allocation failed")
+    return E
+
+
+def interaction_from_mobius_c(a, d: int, l: int, index: str = "fsi", nthreads: int = 1) -> np.ndarray:
+    """Same result as ``interaction_from_mobius`` (same algorithm: superset
+    sums of the given Moebius coefficients), computed by the C twin."""
+    if not (1 <= l <= d):
+        raise ValueError("need 1 <= l <= d")
+    lib = _load()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.size != 1 << d:
+        raise ValueError("a must have 2^d entries")
+    W = np.ascontiguousarray(weight_table_f64(d, l) if index == "fsi"
+                             else index_weight_table_f64(index, d, l))
+    masks = np.ascontiguousarray(output_masks(d, l).astype(np.int64))
+    E = np.empty(masks.size, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int64)
+    lib.oracle_superset_sums(a.ctypes.data_as(dp), d, l, W.ctypes.data_as(dp),
+                             masks.ctypes.data_as(ip), masks.size, E.ctypes.data_as(dp),
+                             int(nthreads))
     return E
 
 

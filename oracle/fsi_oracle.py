@@ -53,6 +53,7 @@ __all__ = [
     "index_weight_exact",
     "index_weight_table_f64",
     "interaction",
+    "interaction_from_mobius",
 ]
 
 
@@ -166,13 +167,14 @@ def fsi(v: np.ndarray, d: int, l: int) -> np.ndarray:
     return _superset_weighted(v, d, l, weight_table_f64(d, l))
 
 
-def _superset_weighted(v, d: int, l: int, W: np.ndarray) -> np.ndarray:
-    """E_S = sum over supersets T of S of W[|S|, |T|] * a(T), a = Moebius(v),
-    for every |S| <= l in canonical order (brute force over (S, T) pairs)."""
+def _superset_weighted(v, d: int, l: int, W: np.ndarray, transform: bool = True) -> np.ndarray:
+    """E_S = sum over supersets T of S of W[|S|, |T|] * a(T), a = Moebius(v)
+    (or a = v when transform is False), for every |S| <= l in canonical order
+    (brute force over (S, T) pairs)."""
     v = np.asarray(v, dtype=np.float64)
     if v.size != 1 << d:
         raise ValueError("v must have 2^d entries")
-    a = mobius(v)
+    a = mobius(v) if transform else v
     out_masks = output_masks(d, l)
     out = np.empty(out_masks.size, dtype=np.float64)
     pc_cache = _popcount(np.arange(1 << d, dtype=np.int64))
@@ -269,3 +271,14 @@ def interaction(v: np.ndarray, d: int, l: int, index: str = "fsi") -> np.ndarray
     if not (1 <= l <= d):
         raise ValueError("need 1 <= l <= d")
     return _superset_weighted(v, d, l, index_weight_table_f64(index, d, l))
+
+
+
+def interaction_from_mobius(a: np.ndarray, d: int, l: int, index: str = "fsi") -> np.ndarray:
+    """The same scores from the Moebius transform a itself (the correction of
+    Eq. 3 - 4 applied to given Moebius coefficients, no butterfly):
+    I_S = sum over supersets T of S of W_index(|S|, |T|) a(T)."""
+    if not (1 <= l <= d):
+        raise ValueError("need 1 <= l <= d")
+    W = weight_table_f64(d, l) if index == "fsi" else index_weight_table_f64(index, d, l)
+    return _superset_weighted(a, d, l, W, transform=False)

@@ -152,8 +152,12 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   fsi_plan_opts opts;
   fsi_default_opts(&opts);
   if (opts_in) opts = *opts_in;
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 1; ++i)
     if (opts.reserved[i] != 0) return fail(FSI_ERR_INVALID_ARG, "reserved option fields must be 0");
+  if (opts.input != FSI_INPUT_VALUES && opts.input != FSI_INPUT_MOBIUS)
+    return fail(FSI_ERR_INVALID_ARG, "unknown input kind");
+  if (opts.input == FSI_INPUT_MOBIUS && opts.algo == FSI_ALGO_TWO_PASS)
+    return fail(FSI_ERR_INVALID_ARG, "Moebius input needs the fused algorithm");
   if (opts.index < FSI_INDEX_FSI || opts.index > FSI_INDEX_BII)
     return fail(FSI_ERR_INVALID_ARG, "unknown interaction index");
   if (opts.kernel < FSI_KERNEL_AUTO || opts.kernel > FSI_KERNEL_REGISTER)
@@ -215,7 +219,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       }
       int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
       if (!want_fast && opts.tile_bits == 0) b = std::max(1, b + sc.tb_shift);
-      std::string err = build_class(dh[i], lh[i], b, algo, opts.index, &C);
+      std::string err = build_class(dh[i], lh[i], b, algo, opts.index, opts.input, &C);
       if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
       const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
                                              ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));
@@ -468,7 +472,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     ClassDev& D = cdev[c];
     D.d = C.d; D.l = C.l; D.b = C.b; D.h = C.h; D.algo = C.algo;
     D.M = C.M; D.Ysize = C.Ysize; D.lam_ublock = C.lam_ublock;
-    D.lds_elems = C.lds_elems; D.nfinal = C.nfinal;
+    D.lds_elems = C.lds_elems; D.nfinal = C.nfinal; D.mobius_in = C.mobius_in;
     D.step_off = reinterpret_cast<const int32_t*>(A + co[c].step_off);
     D.step_np = reinterpret_cast<const int32_t*>(A + co[c].step_np);
     D.pat = reinterpret_cast<const uint32_t*>(A + co[c].pat);
@@ -485,6 +489,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     const FastClassHost& F = P->fclasses[f];
     FastClassDev& D = fdev[f];
     D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk; D.mshift = F.mshift;
+    D.mobius_in = F.mobius_in;
     fast_lds[F.l] = fast_lds_bytes(prec, F.l);
     fast_lds_max = std::max(fast_lds_max, fast_lds[F.l]);
     D.lam = reinterpret_cast<const double*>(A + fo[f].lam);
@@ -622,7 +627,7 @@ std::string tune_key(int n, const int* dh, const int* lh, const fsi_plan_opts& o
   for (int i = 0; i < n; ++i) ++cnt[{dh[i], lh[i]}];
   std::string k = std::to_string(o.dtype) + "/" + std::to_string(o.precision) + "/" +
                   std::to_string(o.algo) + "/" + std::to_string(o.kernel) + "/" +
-                  std::to_string(o.tile_bits);
+                  std::to_string(o.tile_bits) + "/" + std::to_string(o.input);
   for (auto& e : cnt)
     k += ";" + std::to_string(e.first.first) + "," + std::to_string(e.first.second) + "x" +
          std::to_string(e.second);

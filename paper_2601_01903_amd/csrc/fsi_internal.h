@@ -24,6 +24,8 @@ struct ClassDev {
   int32_t lam_ublock;   // doubles per high-popcount block of the weight table
   int32_t lds_elems;    // largest sweep state (entries) of one step
   int32_t nfinal;       // final patterns (S_L, t_L)
+  int32_t mobius_in;    // 1: the input is already the Moebius transform
+  int32_t pad0;
   const int32_t* step_off;  // [b+1] start of step k's entries in pat
   const int32_t* step_np;   // [b+1] number of patterns after step k
   const uint32_t* pat;      // (src0+1) | (src1+1) << 16 per output pattern
@@ -45,6 +47,8 @@ struct FastClassDev {
   int32_t d, l, h, M;
   int32_t nkk;                // slots per thread in use (largest over the output groups)
   int32_t mshift;             // bits of the Y byte offset in a metadata word
+  int32_t mobius_in;          // 1: the input is already the Moebius transform
+  int32_t pad0;
   const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
   const uint32_t* meta;       // [groups * 256 * kFastMetaStride] per group and thread:
                               // Y byte offset | S_H << mshift
@@ -56,7 +60,7 @@ struct FastClassDev {
 };
 
 struct FastClassHost {
-  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16, ngroups = 1;
+  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16, ngroups = 1, mobius_in = 0;
   std::vector<double> lam;
   std::vector<uint32_t> meta, gs8;
   std::vector<int32_t> gnkk;
@@ -84,7 +88,7 @@ struct InstDev {
 
 // Host-side tables of one class (built once, uploaded into a device arena).
 struct ClassHost {
-  int d = 0, l = 0, b = 0, h = 0, algo = ALGO_FUSED;
+  int d = 0, l = 0, b = 0, h = 0, algo = ALGO_FUSED, mobius_in = 0;
   int M = 0, Ysize = 0, lam_ublock = 0, lds_elems = 0, nfinal = 0;
   std::vector<int32_t> step_off, step_np;
   std::vector<uint32_t> pat, ytab, oinfo, osh, out_masks;
@@ -104,7 +108,7 @@ double weight_full(int s, int t, int l, int index);
 // Largest sweep state of an in-tile sweep over b bits, in entries.
 int64_t sweep_peak_entries(int b, int l);
 // Builds all tables for one class; returns "" or an error message.
-std::string build_class(int d, int l, int b, int algo, int index, ClassHost* out);
+std::string build_class(int d, int l, int b, int algo, int index, int mobius_in, ClassHost* out);
 // Output slots per thread the register-phase kernel needs for (d, l), or -1.
 int fast_output_slots(int d, int l);
 // Most high bits (d - 11) the register-phase kernel's output metadata holds at order l.

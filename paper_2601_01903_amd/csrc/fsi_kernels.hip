@@ -103,7 +103,8 @@ tile_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ in
       const SrcT* v = src + I.voff + ((int64_t)w.tile << b);
       for (int i = tid; i < nt; i += NT) m[i] = Num<MobT>::from_in(v[i]);
       __syncthreads();
-      for (int bit = 0; bit < b; ++bit) {
+      // (input already Moebius-transformed: no butterfly)
+      for (int bit = 0; bit < (C->mobius_in ? 0 : b); ++bit) {
         const int half = nt >> 1;
         for (int p = tid; p < half; p += NT) {
           const int lo = ((p >> bit) << (bit + 1)) | (p & ((1 << bit) - 1));

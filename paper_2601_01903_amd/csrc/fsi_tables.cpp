@@ -140,11 +140,12 @@ int64_t sweep_peak_entries(int b, int l) {
   return peak;
 }
 
-std::string build_class(int d, int l, int b, int algo, int index, ClassHost* C) {
+std::string build_class(int d, int l, int b, int algo, int index, int mobius_in, ClassHost* C) {
   if (!(1 <= l && l <= d && d <= kMaxD)) return "invalid (d, l)";
   if (!(1 <= b && b <= kMaxTileBits && b <= d)) return "invalid tile bits";
   const int h = d - b;
-  C->d = d; C->l = l; C->b = b; C->h = h; C->algo = algo;
+  C->d = d; C->l = l; C->b = b; C->h = h; C->algo = algo; C->mobius_in = mobius_in;
+  if (mobius_in && algo != ALGO_FUSED) return "Moebius input needs the fused algorithm";
   C->M = (int)num_outputs(d, l);
 
   // ---- counter states of the in-tile sweep (Sec. 4.3 state space) ----
@@ -238,6 +239,14 @@ std::string build_class(int d, int l, int b, int algo, int index, ClassHost* C) 
         if (algo == ALGO_FUSED) {
           for (int j = 0; j <= sH; ++j) {
             const int slot = sH * (sH + 1) / 2 + j;
+            if (mobius_in) {
+              // input already transformed: a tile with high index U_H feeds
+              // the outputs with S_H inside U_H (j = s_H) at t = t_L + |U_H|
+              const bool ok = j == sH && sH <= u;
+              for (int tL = sL; tL <= b; ++tL)
+                blk[slot * (b + 1) + tL] = ok ? (double)weight_q(s, tL + u, l, index) : 0.0;
+              continue;
+            }
             const bool ok = j <= u && (sH - j) <= (h - u);
             const int q = u + sH - j;
             for (int tL = sL; tL <= b; ++tL)
@@ -289,7 +298,7 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
   if (l > 4) return "register-phase kernel needs l <= 4";
   F->mshift = meta_shift(l);
   if (h > 32 - F->mshift) return "too many high bits for the register-phase kernel";
-  F->d = C.d; F->l = l; F->h = h; F->M = C.M;
+  F->d = C.d; F->l = l; F->h = h; F->M = C.M; F->mobius_in = C.mobius_in;
   // phase-C units and their maps
   const int nu = n3(l);
   F->unit_mask.assign(nu, -1);

@@ -499,6 +499,8 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       reinterpret_cast<const uint4*>(C->meta + ((size_t)grp * NT + tid) * kFastMetaStride);
   const cdptr_u gs8 = (cdptr_u)(C->gs8 + grp * kFastMetaStride);
   const int nkk = GROUPED ? C->gnkk[grp] : C->nkk;
+  // input already Moebius-transformed: the butterflies are skipped
+  const bool mob = __builtin_amdgcn_readfirstlane(C->mobius_in) == 0;
   const int mshift = C->mshift;
   const uint32_t omask = (1u << mshift) - 1u;
   int u_prev = -1;
@@ -536,11 +538,13 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       if constexpr (IN64) xr[c] = mob_from_d<MobT>(xraw[c]);
       else xr[c] = mob_from<MobT>(xraw[c]);
     }
+    if (mob) {
 #pragma unroll
-    for (int bit = 0; bit < PC; ++bit)
+      for (int bit = 0; bit < PC; ++bit)
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        if (c & (1 << bit)) xr[c] = sub(xr[c], xr[c ^ (1 << bit)]);
+        for (int c = 0; c < NC; ++c)
+          if (c & (1 << bit)) xr[c] = sub(xr[c], xr[c ^ (1 << bit)]);
+    }
     {
       MobT* rp = R + (tid & 15) + RB * (tid >> 4);
 #pragma unroll
@@ -553,11 +557,13 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       MobT y[NB];
 #pragma unroll
       for (int b = 0; b < NB; ++b) y[b] = rp[RB * b];
+      if (mob) {
 #pragma unroll
-      for (int bit = 0; bit < PB; ++bit)
+        for (int bit = 0; bit < PB; ++bit)
 #pragma unroll
-        for (int b = 0; b < NB; ++b)
-          if (b & (1 << bit)) y[b] = sub(y[b], y[b ^ (1 << bit)]);
+          for (int b = 0; b < NB; ++b)
+            if (b & (1 << bit)) y[b] = sub(y[b], y[b ^ (1 << bit)]);
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) rp[RB * b] = y[b];
     }
@@ -568,11 +574,13 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       MobT y[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) y[a] = rp[a];
+      if (mob) {
 #pragma unroll
-      for (int bit = 0; bit < PA; ++bit)
+        for (int bit = 0; bit < PA; ++bit)
 #pragma unroll
-        for (int a = 0; a < NA; ++a)
-          if (a & (1 << bit)) y[a] = sub(y[a], y[a ^ (1 << bit)]);
+          for (int a = 0; a < NA; ++a)
+            if (a & (1 << bit)) y[a] = sub(y[a], y[a ^ (1 << bit)]);
+      }
       SwT X1[1][NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) X1[0][a] = to_sw<SwT>(y[a]);

@@ -24,6 +24,7 @@ PRECISIONS = {"f64": 0, "f32": 1, "f32_compensated": 2, "f32_fp64mob": 3,
 ALGOS = {"auto": 0, "fused": 1, "two_pass": 2}
 KERNELS = {"auto": 0, "generic": 1, "register": 2}
 INDICES = {"fsi": 0, "stii": 1, "sii": 2, "ksii": 3, "bii": 4}
+INPUTS = {"values": 0, "mobius": 1}
 
 # names of every function include/fsi.h declares
 EXPORTS = ["fsi_default_opts", "fsi_num_outputs", "fsi_plan", "fsi_plan_ex",
@@ -47,7 +48,7 @@ class Opts(ctypes.Structure):
                 ("algo", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("index", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("input", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class Schedule(ctypes.Structure):
@@ -122,7 +123,8 @@ def num_outputs(d: int, l: int) -> int:
 
 
 def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
-              block_threads=0, kernel="auto", autotune=False, index="fsi") -> Opts:
+              block_threads=0, kernel="auto", autotune=False, index="fsi",
+              input="values") -> Opts:
     o = Opts()
     _check(load().fsi_default_opts(ctypes.byref(o)), "fsi_default_opts")
     o.dtype = DTYPES[dtype]
@@ -133,6 +135,7 @@ def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
     o.kernel = KERNELS[kernel]
     o.autotune = 1 if autotune else 0
     o.index = INDICES[index]
+    o.input = INPUTS[input]
     return o
 
 
@@ -159,12 +162,13 @@ class Plan:
 
     def __init__(self, d: int, l: int, dtype: str = "f64", precision: str = "auto",
                  algo: str = "auto", tile_bits: int = 0, block_threads: int = 0,
-                 kernel: str = "auto", autotune: bool = False, index: str = "fsi"):
+                 kernel: str = "auto", autotune: bool = False, index: str = "fsi",
+                 input: str = "values"):
         lib = load()
         self.d, self.l, self.dtype, self.index = d, l, dtype, index
         self._h = ctypes.c_void_p()
         opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel, autotune,
-                         index)
+                         index, input)
         _check(lib.fsi_plan_ex(d, l, ctypes.byref(opts), ctypes.byref(self._h)), "fsi_plan_ex")
         self.M = num_outputs(d, l)
 
@@ -223,7 +227,7 @@ class BatchPlan:
     def __init__(self, ds: Sequence[int], ls: Sequence[int], dtype: str = "f32",
                  precision: str = "auto", algo: str = "auto", tile_bits: int = 0,
                  block_threads: int = 0, kernel: str = "auto", autotune: bool = False,
-                 index: str = "fsi"):
+                 index: str = "fsi", input: str = "values"):
         lib = load()
         n = len(ds)
         if len(ls) != n:
@@ -233,7 +237,7 @@ class BatchPlan:
         darr = (ctypes.c_int * n)(*ds)
         larr = (ctypes.c_int * n)(*ls)
         opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel, autotune,
-                         index)
+                         index, input)
         self._h = ctypes.c_void_p()
         _check(lib.fsi_plan_batched(n, darr, larr, ctypes.byref(opts), ctypes.byref(self._h)),
                "fsi_plan_batched")

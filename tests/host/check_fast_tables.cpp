@@ -54,7 +54,7 @@ int main() {
       if (!eligible) continue;
       ClassHost C;
       FastClassHost F;
-      std::string e = build_class(d, l, 11, ALGO_FUSED, 0, &C);
+      std::string e = build_class(d, l, 11, ALGO_FUSED, 0, 0, &C);
       CHECK(e.empty(), "d=%d l=%d build_class: %s", d, l, e.c_str());
       if (!e.empty()) continue;
       e = build_fast_class(C, &F);

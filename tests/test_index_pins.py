@@ -227,3 +227,33 @@ def test_index_pins_catch_planted_mistakes(monkeypatch):
         monkeypatch.setattr(F, "index_weight_exact", fn)
         assert not _index_pins_pass(index), index
         monkeypatch.setattr(F, "index_weight_exact", real_w)
+
+
+@pytest.mark.parametrize("index", ["fsi", "stii", "ksii"])
+def test_from_mobius_unanimity_closed_form(index):
+    """Given Moebius coefficients a = delta_A, the scores are the index's
+    weights on the subsets of A: for FSI the unanimity closed form (Eq. 3 +
+    Eq. 4, exact rationals), for all indices the definition-based pins."""
+    d, l = 7, 3
+    rng = np.random.default_rng(17)
+    for A in [0b1011, 0b1110110, 0b101]:
+        a = np.zeros(1 << d)
+        a[A] = 1.0
+        out = oracle.interaction_from_mobius(a, d, l, index)
+        if index == "fsi":
+            assert np.max(np.abs(out - P.fsi_unanimity(A, d, l))) < 1e-15
+        v = np.array([1.0 if (S & A) == A else 0.0 for S in range(1 << d)])
+        assert normwise(out, oracle.interaction(v, d, l, index)) < 1e-15
+    # linear: a random a gives the value vector's scores when v is its zeta transform
+    a = rng.standard_normal(1 << d)
+    v = np.array([sum(a[T] for T in range(1 << d) if T & S == T) for S in range(1 << d)])
+    assert normwise(oracle.interaction_from_mobius(a, d, l, index),
+                    oracle.interaction(v, d, l, index)) < 1e-12
+
+
+def test_from_mobius_c_twin():
+    d, l = 11, 4
+    a = np.random.default_rng(18).standard_normal(1 << d)
+    for index in ("fsi", "sii"):
+        assert normwise(oracle.interaction_from_mobius_c(a, d, l, index),
+                        oracle.interaction_from_mobius(a, d, l, index)) < 1e-14
