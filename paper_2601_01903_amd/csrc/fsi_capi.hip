@@ -591,8 +591,11 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     a.fast.partial = P->partial;
     for (int l = 0; l <= kFastMaxL + 1; ++l) a.fast.lbeg[l] = lbeg[l];
     for (int l = 0; l <= kFastMaxL; ++l) a.fast.grouped[l] = 0;
-    for (const FastClassHost& F : P->fclasses)
+    a.fast.mobius_in = 0;
+    for (const FastClassHost& F : P->fclasses) {
       if (F.ngroups > 1) a.fast.grouped[F.l] = 1;
+      if (F.mobius_in) a.fast.mobius_in = 1;
+    }
     for (int l = 0; l <= kFastMaxL; ++l) {
       a.fast.lds[l] = fast_lds[l];
       const int nl = l >= 1 ? lbeg[l + 1] - lbeg[l] : 0;

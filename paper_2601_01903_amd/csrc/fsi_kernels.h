@@ -43,6 +43,7 @@ struct FastLaunch {
   int grid[kFastMaxL + 1];
   size_t lds[kFastMaxL + 1];
   int grouped[kFastMaxL + 1];     // 1: an instance of this order has several output groups
+  int mobius_in;                  // 1: the input is already the Moebius transform
   const void* vals32;
   const void* vals64;
   const int32_t* torder;

@@ -314,9 +314,10 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
   F->uperm.assign(kFastThreads, 0);
   {
     const UnitOrder uo = mk_unit_order(l);
-    for (int t = 0; t < kFastThreads; ++t) F->uperm[t] = uo.v[t];
-    for (int t = 0; t < nu; ++t)
-      if (uo.v[t] < 0 || uo.v[t] >= nu) return "phase-C unit order out of range";
+    for (int t = 0; t < kFastThreads; ++t) {
+      F->uperm[t] = uo.v[t];
+      if (uo.v[t] < -1 || uo.v[t] >= nu) return "phase-C unit order out of range";
+    }
   }
   F->zrow.assign((size_t)nu * NC, 0);
   for (int u = 0; u < nu; ++u)

@@ -104,28 +104,52 @@ constexpr int unit_index(int L, int sa, int sb) {
 // element (i, unit, c) at ((2 i + c / 4) * n3 + unit) * 4 + c % 4
 constexpr int s2_elems(int L) { return (KAB + 1) * n3(L) * NC; }
 
-// phase-C units in order of |sigma_AB| (stable): thread t of phase C takes
-// unit v[t], so a wave's units share a lower bound kmin[w] on |sigma_AB|
-// (L + 1 for a wave without units)
-struct UnitOrder { int v[NT]; int kmin[NT / 64]; };
+// Phase-C thread map. Units in order of |sigma_AB| (stable). The heavy units
+// (|sigma_AB| <= L - 2: most output prefixes over the C bits) are split at the
+// first C output site: wave 0 walks their sigma = 0 subtree, wave 3 (same
+// lane) their sigma = 1 subtree. The other units fill waves 1 and 2 whole.
+// Thread t takes unit v[t] (-1: idle); every unit of wave w has kmin[w] <=
+// |sigma_AB| <= kmax[w] (kmin = L + 1 for a wave without units).
+struct UnitOrder { int v[NT]; int kmin[NT / 64]; int kmax[NT / 64]; int nheavy; };
 constexpr UnitOrder mk_unit_order(int L) {
   UnitOrder o{};
+  int units[NT] = {}, pop[NT] = {};
   int n = 0;
-  int pop[NT] = {};
   for (int k = 0; k <= L; ++k)
     for (int sb = 0; sb < NB; ++sb)
       for (int r = 0; r < NA; ++r) {
         const int sa = orderA(r);
         if (cpop(sa) + cpop(sb) == k) {
-          o.v[n] = ubase(L, sb) + r;
+          units[n] = ubase(L, sb) + r;
           pop[n] = k;
           ++n;
         }
       }
-  for (int t = n; t < NT; ++t) o.v[t] = 0;
-  for (int w = 0; w < NT / 64; ++w) o.kmin[w] = 64 * w < n ? pop[64 * w] : L + 1;
+  int nh = 0;
+  while (nh < n && pop[nh] <= L - 2) ++nh;
+  for (int t = 0; t < NT; ++t) o.v[t] = -1;
+  for (int i = 0; i < nh; ++i) o.v[i] = o.v[3 * 64 + i] = units[i];
+  for (int i = nh; i < n; ++i) o.v[64 + i - nh] = units[i];
+  o.nheavy = nh;
+  for (int w = 0; w < NT / 64; w += 3) {   // waves 0 and 3
+    o.kmin[w] = nh ? 0 : L + 1;
+    o.kmax[w] = nh ? pop[nh - 1] : L + 1;
+  }
+  for (int w = 1; w <= 2; ++w) {
+    const int i0 = nh + 64 * (w - 1), i1 = imin(n, i0 + 64);
+    o.kmin[w] = i0 < n ? pop[i0] : L + 1;
+    o.kmax[w] = i0 < n ? pop[i1 - 1] : L + 1;
+  }
   return o;
 }
+// the map fits the workgroup at every order the kernel runs
+constexpr bool unit_order_fits(int L) {
+  int heavy = 0, rest = 0;
+  for (int k = 0; k <= L; ++k) (k <= L - 2 ? heavy : rest) += cbinom(KAB, k);
+  return heavy <= 64 && rest <= 128;
+}
+static_assert(unit_order_fits(1) && unit_order_fits(2) && unit_order_fits(3) &&
+              unit_order_fits(4), "phase-C units exceed the workgroup");
 
 // ---- Z rows ----
 constexpr int zbase(int s) {

@@ -200,16 +200,16 @@ struct EmitS2 {
 };
 
 // Phase C -> Z row of S_L = sigma_AB | sigma_C << 8 (12 entries, zero padded).
-template <typename SwT, int L, int KMIN>
+template <typename SwT, int L, int KMIN, int KMAX>
 struct EmitZ {
   SwT* Z;
   const int (&zr)[NC];   // Z row per sigma_C (dump row where |S_L| > L)
-  int sAB;               // >= KMIN for every unit of the wave
+  int sAB;               // in [KMIN, KMAX] for every unit of the wave
   template <int SIG, int LO, int RC>
   __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
     constexpr int sC = cpop(SIG);
     if constexpr (sC <= L - KMIN) {
-      if (sAB <= L - sC) {
+      if (sC <= L - KMAX || sAB <= L - sC) {
         using V = typename Vec4<SwT>::type;
         constexpr int VN = Vec4<SwT>::n;
         V* p = reinterpret_cast<V*>(Z + zr[SIG] * ZROW);
@@ -415,7 +415,13 @@ __device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r
 
 template <int L> struct UO { static constexpr UnitOrder o = mk_unit_order(L); };
 
-template <int L, int KMIN, typename SwT>
+// Phase C of one wave: its units have KMIN <= |sigma_AB| <= KMAX. Counter
+// rows past KAB - |sigma_AB| are zero: dropped at compile time past
+// KAB - KMIN, and below that read as zeros (a zeroed LDS row where KMIN = 0,
+// so the loads issue without branches). PART 2 walks all output prefixes over
+// the C bits; PART 0 the sigma = 0 subtree of the first C site (all 8
+// inputs), PART 1 its sigma = 1 subtree (the 4 tau = 1 inputs).
+template <int L, int KMIN, int KMAX, int PART, typename SwT>
 __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[NC], int sAB,
                                         int u3, const SwT* zrow) {
   if constexpr (KMIN <= L) {
@@ -423,43 +429,61 @@ __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[N
     constexpr int VN = Vec4<SwT>::n;
     constexpr int N3 = K<L>::N3;
     constexpr int NR = KAB + 1 - KMIN;
-    SwT X3[NR][NC];
+    constexpr int H0 = PART == 1 ? 1 : 0;       // first half (c / 4) read
+    constexpr int W = PART == 1 ? NC / 2 : NC;  // inputs read
+    SwT X3[NR][W];
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
-      if (KMIN > 0 && i > KAB - sAB) {   // past this unit's counters: zero, not read
+      const bool in = i <= KAB - KMAX || i <= KAB - sAB;
+      if (KMIN > 0 && !in) {   // past this unit's counters: zero, not read
 #pragma unroll
-        for (int c = 0; c < NC; ++c) X3[i][c] = SwT(0);
+        for (int c = 0; c < W; ++c) X3[i][c] = SwT(0);
         continue;
       }
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = H0; h < 2; ++h) {
         const V* src = reinterpret_cast<const V*>(
-            KMIN > 0 || i <= KAB - sAB ? S2 + ((2 * i + h) * N3 + u3) * 4 : zrow);
+            KMIN > 0 || in ? S2 + ((2 * i + h) * N3 + u3) * 4 : zrow);
 #pragma unroll
         for (int q = 0; q < 4 / VN; ++q) {
           const V v = src[q];
+          const int c0 = 4 * (h - H0) + VN * q;
           if constexpr (VN == 4) {
-            X3[i][4 * h] = v.x; X3[i][4 * h + 1] = v.y; X3[i][4 * h + 2] = v.z; X3[i][4 * h + 3] = v.w;
+            X3[i][c0] = v.x; X3[i][c0 + 1] = v.y; X3[i][c0 + 2] = v.z; X3[i][c0 + 3] = v.w;
           } else {
-            X3[i][4 * h + 2 * q] = v.x; X3[i][4 * h + 2 * q + 1] = v.y;
+            X3[i][c0] = v.x; X3[i][c0 + 1] = v.y;
           }
         }
       }
     }
-    EmitZ<SwT, L, KMIN> ez{Z, zr, sAB};
-    rsweep<PC, 0, NR, 0>(X3, ez);
+    EmitZ<SwT, L, KMIN, KMAX> ez{Z, zr, sAB};
+    if constexpr (PART == 2) {
+      rsweep<PC, 0, NR, 0>(X3, ez);
+    } else if constexpr (PART == 0) {
+      constexpr int H = NC / 2;
+      SwT Y0[NR + 1][H];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        Y0[0][j] = X3[0][j];
+#pragma unroll
+        for (int t = 1; t < NR; ++t) Y0[t][j] = X3[t][j] + X3[t - 1][H + j];
+        Y0[NR][j] = X3[NR - 1][H + j];
+      }
+      rsweep<PC - 1, 0, NR + 1, 0>(Y0, ez);
+    } else {
+      rsweep<PC - 1, 1, NR, NC / 2>(X3, ez);
+    }
   }
 }
 
 // ------------------------------------------------------------------ item
-template <int L, typename SwT, typename MobT, bool IN64, bool GROUPED>
+template <int L, typename SwT, typename MobT, bool IN64, bool GROUPED, bool MOBIN>
 __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, const InstDev& I,
                                          const FastItem& W, const float* __restrict__ vals32,
                                          const double* __restrict__ vals64,
                                          const int32_t* __restrict__ torder,
                                          double* __restrict__ partial, unsigned char* smem) {
   constexpr int KMAX = kFastKmax;
-  constexpr int R1 = row1_stride<SwT>();
   constexpr int N3 = K<L>::N3;
   constexpr int LB = K<L>::LB;
   using LD = Lds<L, SwT, MobT>;
@@ -482,7 +506,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const int sA = __popc(sA_mask);
   const int wb = ((p2c >> 2) * N3 + p2r) * 4 + (p2c & 3);
   // phase C: thread = unit
-  const int u3 = tid < N3 ? C->uperm[tid] : 0;
+  const int u3r = C->uperm[tid];
+  const bool c_on = u3r >= 0;   // this thread has a phase-C unit
+  const int u3 = c_on ? u3r : 0;
   const int sAB = __popc(C->unit_mask[u3]);
   int zr[NC];
 #pragma unroll
@@ -499,8 +525,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       reinterpret_cast<const uint4*>(C->meta + ((size_t)grp * NT + tid) * kFastMetaStride);
   const cdptr_u gs8 = (cdptr_u)(C->gs8 + grp * kFastMetaStride);
   const int nkk = GROUPED ? C->gnkk[grp] : C->nkk;
-  // input already Moebius-transformed: the butterflies are skipped
-  const bool mob = __builtin_amdgcn_readfirstlane(C->mobius_in) == 0;
+  // input already Moebius-transformed (a separate instantiation): the
+  // butterflies are skipped
+  constexpr bool mob = !MOBIN;
   const int mshift = C->mshift;
   const uint32_t omask = (1u << mshift) - 1u;
   int u_prev = -1;
@@ -600,14 +627,16 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       default: phase_b<L, kSAHi, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
     }
     __syncthreads();
-    // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|),
-    // counters relative to |sigma_AB| ----
-    if (tid < N3) {
+    // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|,
+    // the heavy ones split between waves 0 and 3), counters relative to
+    // |sigma_AB| ----
+    if (c_on) {
+      using O = UO<L>;
       switch (wave) {
-        case 0: phase_c<L, UO<L>::o.kmin[0], SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        case 1: phase_c<L, UO<L>::o.kmin[1], SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        case 2: phase_c<L, UO<L>::o.kmin[2], SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        default: phase_c<L, UO<L>::o.kmin[3], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 0: phase_c<L, O::o.kmin[0], O::o.kmax[0], 0, SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 1: phase_c<L, O::o.kmin[1], O::o.kmax[1], 2, SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 2: phase_c<L, O::o.kmin[2], O::o.kmax[2], 2, SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        default: phase_c<L, O::o.kmin[3], O::o.kmax[3], 1, SwT>(S2, Z, zr, sAB, u3, zrow); break;
       }
     }
     // prefetch the next tile and this tile's output metadata while the
@@ -662,7 +691,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
 // One kernel per order l (the items of a launch all have that order).
 // FP32 sweep: two workgroups per CU (2 waves per SIMD), so at most 256 VGPRs
 // per thread; the FP64 sweep's LDS allows one workgroup per CU.
-template <int L, typename SwT, typename MobT, bool IN64, int WPE, bool GROUPED>
+template <int L, typename SwT, typename MobT, bool IN64, int WPE, bool GROUPED, bool MOBIN>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               const FastItem* __restrict__ items, int n_items,
@@ -678,7 +707,7 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
-    run_item<L, SwT, MobT, IN64, GROUPED>(classes + I.fcls, I, W, vals32, vals64, torder, partial,
+    run_item<L, SwT, MobT, IN64, GROUPED, MOBIN>(classes + I.fcls, I, W, vals32, vals64, torder, partial,
                                           smem);
     __syncthreads();
   }
@@ -699,14 +728,15 @@ template <typename SwT> constexpr int wpe_for() { return sizeof(SwT) == 4 ? 2 : 
 
 // Output groups occur only at l = 4 (lower orders need at most 20 slots
 // per thread), so only that order has a grouped instantiation; a launch
-// uses it when one of its instances has more than one group.
-template <int L, typename SwT, typename MobT, bool IN64>
-static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
+// uses it when one of its instances has more than one group. Plans whose
+// input is already the Moebius transform run their own instantiations.
+template <int L, typename SwT, typename MobT, bool IN64, bool MOBIN>
+static hipError_t launch_t11_m(const FastLaunch& f, hipStream_t st) {
   const int ib = f.lbeg[L], n = f.lbeg[L + 1] - f.lbeg[L];
   if (n <= 0) return hipSuccess;
-  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false>;
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
   if constexpr (L == kFastMaxL)
-    if (f.grouped[L]) k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true>;
+    if (f.grouped[L]) k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>;
   hipLaunchKernelGGL(k, dim3(f.grid[L]), dim3(t11::NT), f.lds[L], st, f.classes, f.insts,
                      f.items + ib, n, static_cast<const float*>(f.vals32),
                      static_cast<const double*>(f.vals64), f.torder, f.partial);
@@ -714,17 +744,30 @@ static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
 }
 
 template <int L, typename SwT, typename MobT, bool IN64>
-static hipError_t config_t11(size_t lds) {
-  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false>;
+static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
+  return f.mobius_in ? launch_t11_m<L, SwT, MobT, IN64, true>(f, st)
+                     : launch_t11_m<L, SwT, MobT, IN64, false>(f, st);
+}
+
+template <int L, typename SwT, typename MobT, bool IN64, bool MOBIN>
+static hipError_t config_t11_m(size_t lds) {
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if constexpr (L == kFastMaxL) {
     if (e != hipSuccess) return e;
-    auto kg = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true>;
+    auto kg = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(kg),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   }
   return e;
+}
+
+template <int L, typename SwT, typename MobT, bool IN64>
+static hipError_t config_t11(size_t lds) {
+  hipError_t e = config_t11_m<L, SwT, MobT, IN64, false>(lds);
+  if (e != hipSuccess) return e;
+  return config_t11_m<L, SwT, MobT, IN64, true>(lds);
 }
 
 template <typename SwT, typename MobT, bool IN64>

@@ -25,25 +25,38 @@ static int fails = 0;
   } while (0)
 
 int main() {
-  // unit order of phase C: a permutation of the units, each wave's units at
-  // or above its compile-time bound on |sigma_AB|
+  // phase-C thread map: every unit once in waves 1-2, or (heavy units) on
+  // the same lane of waves 0 and 3; each wave's units within its
+  // compile-time bounds on |sigma_AB|; heavy units have |sigma_AB| <= L - 2
   for (int L = 1; L <= 4; ++L) {
     const UnitOrder o = mk_unit_order(L);
-    std::set<int> seen;
+    std::vector<int> count(n3(L), 0);
     int last_pop = -1;
-    for (int t = 0; t < n3(L); ++t) {
-      seen.insert(o.v[t]);
+    for (int t = 0; t < NT; ++t) {
+      const int w = t / 64, u = o.v[t];
+      if (u < 0) continue;
+      CHECK(u < n3(L), "L=%d thread %d: unit %d out of range", L, t, u);
+      if (u >= n3(L)) continue;
       int pop = -1;
       for (int sb = 0; sb < NB; ++sb)
         for (int sa = 0; sa < NA; ++sa)
-          if (unit_index(L, sa, sb) == o.v[t]) pop = cpop(sa) + cpop(sb);
-      CHECK(pop >= 0, "L=%d thread %d: not a unit", L, t);
-      CHECK(pop >= last_pop, "L=%d: units not in order of |sigma_AB|", L);
-      CHECK(pop >= o.kmin[t / 64], "L=%d thread %d: |sigma_AB| %d below the wave bound %d", L, t,
-            pop, o.kmin[t / 64]);
-      last_pop = pop;
+          if (unit_index(L, sa, sb) == u) pop = cpop(sa) + cpop(sb);
+      CHECK(pop >= o.kmin[w] && pop <= o.kmax[w],
+            "L=%d thread %d: |sigma_AB| %d outside the wave bounds [%d, %d]", L, t, pop,
+            o.kmin[w], o.kmax[w]);
+      if (w == 0) {
+        CHECK(pop <= L - 2, "L=%d thread %d: split unit with |sigma_AB| %d", L, t, pop);
+        CHECK(o.v[t + 192] == u, "L=%d lane %d: halves of a split unit on different lanes", L, t);
+      }
+      if (w == 3) CHECK(o.v[t - 192] == u, "L=%d thread %d: half without its partner", L, t);
+      if (w == 1 || w == 2) {
+        CHECK(pop > L - 2, "L=%d thread %d: heavy unit not split", L, t);
+        CHECK(pop >= last_pop, "L=%d: units not in order of |sigma_AB|", L);
+        last_pop = pop;
+      }
+      if (w != 3) ++count[u];
     }
-    CHECK((int)seen.size() == n3(L), "L=%d: unit order is not a permutation", L);
+    for (int u = 0; u < n3(L); ++u) CHECK(count[u] == 1, "L=%d unit %d taken %d times", L, u, count[u]);
   }
   // every eligible (d, l): tables build, each canonical output decodes to its
   // own mask from the metadata word, and the slots are a bijection
