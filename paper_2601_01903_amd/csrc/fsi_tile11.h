@@ -101,8 +101,13 @@ constexpr int n3(int L) { return ubase(L, NB); }
 constexpr int unit_index(int L, int sa, int sb) {
   return cpop(sa) + cpop(sb) > L ? -1 : ubase(L, sb) + rankA(sa);
 }
-// element (i, unit, c) at ((2 i + c / 4) * n3 + unit) * 4 + c % 4
-constexpr int s2_elems(int L) { return (KAB + 1) * n3(L) * NC; }
+// element (i, unit, c) at ((2 i + c / 4) * s2u + unit) * 4 + c % 4, with the
+// unit count padded to s2u, a multiple of 8: the counter rows of one
+// (unit, c) lie a multiple of 64 elements apart, so their stores pair up
+// (two per instruction), and the two c-halves of a phase-B wave fall on
+// disjoint LDS banks
+constexpr int s2u(int L) { return (n3(L) + 7) & ~7; }
+constexpr int s2_elems(int L) { return (KAB + 1) * s2u(L) * NC; }
 
 // Phase-C thread map. Units in order of |sigma_AB| (stable). The heavy units
 // (|sigma_AB| <= L - 2: most output prefixes over the C bits) are split at the

@@ -13,9 +13,11 @@
 //     phase's output bits depth first: each output state adds its tau = 0
 //     and tau = 1 predecessors (the sparse MPO cores). Between phases the
 //     (sigma, t) states go through LDS, truncated to |sigma| <= l (the
-//     compressed output prefix). In phases B and C the threads are ordered
-//     so that each wave's prefixes share a lower bound on their popcount, and
-//     each wave runs code compiled for that bound;
+//     compressed output prefix). Phase B splits its first output site
+//     between the two halves of the workgroup (sigma = 0 and sigma = 1
+//     subtrees); phase C splits it for its heavy prefixes only. Threads are
+//     ordered so that each wave's prefixes share bounds on their popcount,
+//     and each wave runs code compiled for those bounds;
 //   - the final weight core with the Moebius cores of the high sites
 //     precontracted into it (Sec. 4.5 applied to the high sites), in FP64:
 //     Y[S_L, s_H, j] = sum_t lambda_u(s_L + s_H, t, s_H + u - j) Z[S_L, t],
@@ -154,6 +156,7 @@ struct K {
   static constexpr A16 ub = mk_ubase(L);
   static constexpr A16 rk = mk_rank();
   static constexpr int N3 = n3(L);
+  static constexpr int S2U = s2u(L);
   static constexpr int LB = lamblock(L);
   static constexpr int NTASK = ntasks(L);
   static constexpr int NPAIR = npairs(L);
@@ -191,9 +194,9 @@ struct EmitS2 {
     if constexpr (sB <= L - SAMIN) {
       if (sA <= L - sB) {
         constexpr int UB = K<L>::ub.v[SIG];
-        constexpr int N3 = K<L>::N3;
+        constexpr int S2U = K<L>::S2U;
 #pragma unroll
-        for (int i = 0; i < RC; ++i) S2[(2 * i * N3 + UB) * 4] = X[i][0];
+        for (int i = 0; i < RC; ++i) S2[(2 * i * S2U + UB) * 4] = X[i][0];
       }
     }
   }
@@ -356,9 +359,6 @@ __device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, cons
   }
 }
 
-// Phase C of one wave: every unit of the wave has |sigma_AB| >= KMIN, so its
-// counter rows past KAB - KMIN are zero and its leaves with |sigma_C| >
-// L - KMIN are never written: both are dropped at compile time.
 // Phase B of one wave: every sigma_A of the wave has |sigma_A| >= SAMIN, so
 // its counter rows past PA - SAMIN are zero and its leaves with |sigma_B| >
 // L - SAMIN are never written. HALF 0 walks the sigma = 0 subtree of the
@@ -427,7 +427,7 @@ __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[N
   if constexpr (KMIN <= L) {
     using V = typename Vec4<SwT>::type;
     constexpr int VN = Vec4<SwT>::n;
-    constexpr int N3 = K<L>::N3;
+    constexpr int S2U = K<L>::S2U;
     constexpr int NR = KAB + 1 - KMIN;
     constexpr int H0 = PART == 1 ? 1 : 0;       // first half (c / 4) read
     constexpr int W = PART == 1 ? NC / 2 : NC;  // inputs read
@@ -443,7 +443,7 @@ __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[N
 #pragma unroll
       for (int h = H0; h < 2; ++h) {
         const V* src = reinterpret_cast<const V*>(
-            KMIN > 0 || in ? S2 + ((2 * i + h) * N3 + u3) * 4 : zrow);
+            KMIN > 0 || in ? S2 + ((2 * i + h) * S2U + u3) * 4 : zrow);
 #pragma unroll
         for (int q = 0; q < 4 / VN; ++q) {
           const V v = src[q];
@@ -484,7 +484,6 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
                                          const int32_t* __restrict__ torder,
                                          double* __restrict__ partial, unsigned char* smem) {
   constexpr int KMAX = kFastKmax;
-  constexpr int N3 = K<L>::N3;
   constexpr int LB = K<L>::LB;
   using LD = Lds<L, SwT, MobT>;
   MobT* R = reinterpret_cast<MobT*>(smem);
@@ -504,7 +503,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const int p2r = (((tid & 127) >> 6) << 3) | (tid & 7), p2c = (tid >> 3) & 7;
   const int sA_mask = (int)((kOrderANibbles >> (4 * p2r)) & 15u);
   const int sA = __popc(sA_mask);
-  const int wb = ((p2c >> 2) * N3 + p2r) * 4 + (p2c & 3);
+  const int wb = ((p2c >> 2) * K<L>::S2U + p2r) * 4 + (p2c & 3);
   // phase C: thread = unit
   const int u3r = C->uperm[tid];
   const bool c_on = u3r >= 0;   // this thread has a phase-C unit
