@@ -111,11 +111,20 @@ constexpr int s2_elems(int L) { return (KAB + 1) * s2u(L) * NC; }
 
 // Phase-C thread map. Units in order of |sigma_AB| (stable). The heavy units
 // (|sigma_AB| <= L - 2: most output prefixes over the C bits) are split at the
-// first C output site: wave 0 walks their sigma = 0 subtree, wave 3 (same
-// lane) their sigma = 1 subtree. The other units fill waves 1 and 2 whole.
-// Thread t takes unit v[t] (-1: idle); every unit of wave w has kmin[w] <=
-// |sigma_AB| <= kmax[w] (kmin = L + 1 for a wave without units).
-struct UnitOrder { int v[NT]; int kmin[NT / 64]; int kmax[NT / 64]; int nheavy; };
+// first C output site: wave kCWaveH0 walks their sigma = 0 subtree, wave
+// kCWaveH1 (same lane) their sigma = 1 subtree. The other units fill waves
+// kCWaveR0 and kCWaveR1 whole. Thread t takes unit v[t] (-1: idle); every
+// unit of wave w has kmin[w] <= |sigma_AB| <= kmax[w] (kmin = L + 1 for a
+// wave without units) and wave w walks part[w] of the C-site tree (0: sigma
+// = 0 subtree, 1: sigma = 1 subtree, 2: all). The roles are placed so that
+// each SIMD's share of the per-tile work (one wave of each workgroup per
+// SIMD) comes out about even over the phases.
+constexpr int kCWaveH0 = 1, kCWaveH1 = 3, kCWaveR0 = 0, kCWaveR1 = 2;
+struct UnitOrder {
+  int v[NT];
+  int kmin[NT / 64], kmax[NT / 64], part[NT / 64];
+  int nheavy;
+};
 constexpr UnitOrder mk_unit_order(int L) {
   UnitOrder o{};
   int units[NT] = {}, pop[NT] = {};
@@ -133,15 +142,18 @@ constexpr UnitOrder mk_unit_order(int L) {
   int nh = 0;
   while (nh < n && pop[nh] <= L - 2) ++nh;
   for (int t = 0; t < NT; ++t) o.v[t] = -1;
-  for (int i = 0; i < nh; ++i) o.v[i] = o.v[3 * 64 + i] = units[i];
-  for (int i = nh; i < n; ++i) o.v[64 + i - nh] = units[i];
+  for (int i = 0; i < nh; ++i) o.v[64 * kCWaveH0 + i] = o.v[64 * kCWaveH1 + i] = units[i];
+  for (int i = nh; i < n; ++i)
+    o.v[64 * (i - nh < 64 ? kCWaveR0 : kCWaveR1) + (i - nh) % 64] = units[i];
   o.nheavy = nh;
-  for (int w = 0; w < NT / 64; w += 3) {   // waves 0 and 3
-    o.kmin[w] = nh ? 0 : L + 1;
-    o.kmax[w] = nh ? pop[nh - 1] : L + 1;
-  }
-  for (int w = 1; w <= 2; ++w) {
-    const int i0 = nh + 64 * (w - 1), i1 = imin(n, i0 + 64);
+  o.part[kCWaveH0] = 0;
+  o.part[kCWaveH1] = 1;
+  o.part[kCWaveR0] = o.part[kCWaveR1] = 2;
+  o.kmin[kCWaveH0] = o.kmin[kCWaveH1] = nh ? 0 : L + 1;
+  o.kmax[kCWaveH0] = o.kmax[kCWaveH1] = nh ? pop[nh - 1] : L + 1;
+  for (int q = 0; q < 2; ++q) {
+    const int w = q ? kCWaveR1 : kCWaveR0;
+    const int i0 = nh + 64 * q, i1 = imin(n, i0 + 64);
     o.kmin[w] = i0 < n ? pop[i0] : L + 1;
     o.kmax[w] = i0 < n ? pop[i1 - 1] : L + 1;
   }

@@ -594,9 +594,12 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       for (int b = 0; b < NB; ++b) rp[RB * b] = y[b];
     }
     __syncthreads();
-    // ---- Moebius over bits 0-3 + phase A: thread (b, c) holds the 16 a values ----
-    if (tid < NB * NC) {
-      const MobT* rp = R + RB * (tid & 15) + RC_ * (tid >> 4);
+    // ---- Moebius over bits 0-3 + phase A: thread (b, c) of waves 2-3 holds
+    // the 16 a values (waves 0-1 ran the B bits: the two-wave steps are
+    // spread over all four SIMDs) ----
+    if (tid >= NT - NB * NC) {
+      const int ta = tid - (NT - NB * NC);
+      const MobT* rp = R + RB * (ta & 15) + RC_ * (ta >> 4);
       MobT y[NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) y[a] = rp[a];
@@ -610,7 +613,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       SwT X1[1][NA];
 #pragma unroll
       for (int a = 0; a < NA; ++a) X1[0][a] = to_sw<SwT>(y[a]);
-      EmitS1<SwT, L> e1{S1 + tid};
+      EmitS1<SwT, L> e1{S1 + ta};
       rsweep<PA, 0, 1, 0>(X1, e1);
     }
     __syncthreads();
@@ -627,15 +630,15 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     }
     __syncthreads();
     // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|,
-    // the heavy ones split between waves 0 and 3), counters relative to
+    // the heavy ones split between two waves), counters relative to
     // |sigma_AB| ----
     if (c_on) {
       using O = UO<L>;
       switch (wave) {
-        case 0: phase_c<L, O::o.kmin[0], O::o.kmax[0], 0, SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        case 1: phase_c<L, O::o.kmin[1], O::o.kmax[1], 2, SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        case 2: phase_c<L, O::o.kmin[2], O::o.kmax[2], 2, SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        default: phase_c<L, O::o.kmin[3], O::o.kmax[3], 1, SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 0: phase_c<L, O::o.kmin[0], O::o.kmax[0], O::o.part[0], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 1: phase_c<L, O::o.kmin[1], O::o.kmax[1], O::o.part[1], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 2: phase_c<L, O::o.kmin[2], O::o.kmax[2], O::o.part[2], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        default: phase_c<L, O::o.kmin[3], O::o.kmax[3], O::o.part[3], SwT>(S2, Z, zr, sAB, u3, zrow); break;
       }
     }
     // prefetch the next tile and this tile's output metadata while the

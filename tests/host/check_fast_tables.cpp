@@ -25,11 +25,19 @@ static int fails = 0;
   } while (0)
 
 int main() {
-  // phase-C thread map: every unit once in waves 1-2, or (heavy units) on
-  // the same lane of waves 0 and 3; each wave's units within its
-  // compile-time bounds on |sigma_AB|; heavy units have |sigma_AB| <= L - 2
+  // phase-C thread map: every unit once in the whole-tree waves, or (heavy
+  // units) on the same lane of the two half-tree waves; each wave's units
+  // within its compile-time bounds on |sigma_AB|; heavy units have
+  // |sigma_AB| <= L - 2
   for (int L = 1; L <= 4; ++L) {
     const UnitOrder o = mk_unit_order(L);
+    int half[2] = {-1, -1};
+    for (int w = 0; w < NT / 64; ++w) {
+      CHECK(o.part[w] >= 0 && o.part[w] <= 2, "L=%d wave %d: part %d", L, w, o.part[w]);
+      if (o.part[w] < 2) half[o.part[w]] = w;
+    }
+    CHECK(half[0] >= 0 && half[1] >= 0, "L=%d: the two half-tree waves are missing", L);
+    if (half[0] < 0 || half[1] < 0) continue;
     std::vector<int> count(n3(L), 0);
     int last_pop = -1;
     for (int t = 0; t < NT; ++t) {
@@ -44,18 +52,29 @@ int main() {
       CHECK(pop >= o.kmin[w] && pop <= o.kmax[w],
             "L=%d thread %d: |sigma_AB| %d outside the wave bounds [%d, %d]", L, t, pop,
             o.kmin[w], o.kmax[w]);
-      if (w == 0) {
+      if (o.part[w] < 2) {
         CHECK(pop <= L - 2, "L=%d thread %d: split unit with |sigma_AB| %d", L, t, pop);
-        CHECK(o.v[t + 192] == u, "L=%d lane %d: halves of a split unit on different lanes", L, t);
-      }
-      if (w == 3) CHECK(o.v[t - 192] == u, "L=%d thread %d: half without its partner", L, t);
-      if (w == 1 || w == 2) {
+        const int partner = 64 * half[1 - o.part[w]] + t % 64;
+        CHECK(o.v[partner] == u, "L=%d thread %d: half without its partner", L, t);
+        if (o.part[w] == 0) ++count[u];
+      } else {
         CHECK(pop > L - 2, "L=%d thread %d: heavy unit not split", L, t);
-        CHECK(pop >= last_pop, "L=%d: units not in order of |sigma_AB|", L);
-        last_pop = pop;
+        ++count[u];
       }
-      if (w != 3) ++count[u];
     }
+    // whole-tree units in order of |sigma_AB| across the two waves
+    for (int q = 0; q < 2; ++q)
+      for (int w = 0; w < NT / 64; ++w)
+        if (o.part[w] == 2 && ((q == 0) == (w == kCWaveR0)))
+          for (int t = 64 * w; t < 64 * w + 64; ++t) {
+            if (o.v[t] < 0) continue;
+            int pop = -1;
+            for (int sb = 0; sb < NB; ++sb)
+              for (int sa = 0; sa < NA; ++sa)
+                if (unit_index(L, sa, sb) == o.v[t]) pop = cpop(sa) + cpop(sb);
+            CHECK(pop >= last_pop, "L=%d: units not in order of |sigma_AB|", L);
+            last_pop = pop;
+          }
     for (int u = 0; u < n3(L); ++u) CHECK(count[u] == 1, "L=%d unit %d taken %d times", L, u, count[u]);
   }
   // every eligible (d, l): tables build, each canonical output decodes to its
