@@ -332,7 +332,14 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       if (pos >= ((int64_t)1 << 31)) { free_batch(P); return fail(FSI_ERR_INTERNAL, "partial sums too large"); }
       fpidx[f][k] = (int32_t)pos;
     }
-  }  std::vector<int2> red_chunks;
+  }
+  // reduction of the register-phase partial sums: one output per thread when
+  // no instance has more than two items per output, else four item rows
+  int red_rows = 1;
+  for (int i = 0; i < n; ++i)
+    if (insts[i].fast && insts[i].nitems > 2) red_rows = 4;
+  const int red_width = kFastThreads / red_rows;
+  std::vector<int2> red_chunks;
   int n_generic = 0;
   for (int i = 0; i < n; ++i) {
     if (!insts[i].fast) {
@@ -342,7 +349,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       continue;
     }
     const int Mi = P->classes[P->cls_of[i]].M;
-    for (int k0 = 0; k0 < Mi; k0 += 64) red_chunks.push_back(make_int2(i, k0));
+    for (int k0 = 0; k0 < Mi; k0 += red_width) red_chunks.push_back(make_int2(i, k0));
   }
   // wide gather items: per instance, output groups x tile ranges; the ranges
   // (a power of two) give the machine about two items per CU
@@ -577,6 +584,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.wide_partial = P->wide_partial;
   a.red_chunks = reinterpret_cast<const int2*>(A + o_red);
   a.n_red_chunks = (int)red_chunks.size();
+  a.red_rows = red_rows;
   a.grid_red_chunks = std::max(1, std::min<int>((int)red_chunks.size(), n_cu * 8));
   a.fast = FastLaunch{};
   a.fast.n_items = (int)fitems.size();

@@ -278,16 +278,19 @@ wide_final_kernel(const WideGroup* __restrict__ groups, int n_groups,
 }
 
 // Sum of the register-phase kernel's per-item partial results. A workgroup
-// owns 64 outputs of one instance; thread (o, r) adds the items j = r mod 4
-// in increasing order, then the four sums are combined in a fixed order, so
-// the result is bitwise repeatable.
-template <typename OutT>
+// owns 256 / ROWS outputs of one instance; thread (o, r) adds the items
+// j = r mod ROWS in increasing order, then the ROWS sums are combined in a
+// fixed order, so the result is bitwise repeatable. ROWS = 1 when every
+// instance has at most two items per output (the usual batched case: one
+// output per thread, no LDS step), else 4.
+template <typename OutT, int ROWS>
 __global__ void __launch_bounds__(256)
 fast_reduce_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ chunks,
                    int n_chunks, const int64_t* __restrict__ out_offset,
                    const double* __restrict__ partial, OutT* __restrict__ out) {
-  __shared__ double part[4][64];
-  const int o = threadIdx.x & 63, r = threadIdx.x >> 6;
+  constexpr int W = 256 / ROWS;
+  __shared__ double part[ROWS][W];
+  const int o = threadIdx.x % W, r = threadIdx.x / W;
   for (int ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const int2 c = chunks[ch];
     const InstDev I = insts[c.x];
@@ -296,13 +299,21 @@ fast_reduce_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ c
     double acc = 0.0;
     if (k < M) {
       const double* P = partial + I.pbase + I.pidx[k];
-      for (int j = r; j < I.nitems; j += 4) acc += P[(int64_t)j * I.pstride];
+      for (int j = r; j < I.nitems; j += ROWS) acc += P[(int64_t)j * I.pstride];
     }
-    part[r][o] = acc;
-    __syncthreads();
-    if (r == 0 && k < M)
-      out[I.ooff + k] = (OutT)(((part[0][o] + part[1][o]) + part[2][o]) + part[3][o]);
-    __syncthreads();
+    if constexpr (ROWS == 1) {
+      if (k < M) out[I.ooff + k] = (OutT)acc;
+    } else {
+      part[r][o] = acc;
+      __syncthreads();
+      if (r == 0 && k < M) {
+        double t = part[0][o];
+#pragma unroll
+        for (int q = 1; q < ROWS; ++q) t += part[q][o];
+        out[I.ooff + k] = (OutT)t;
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -440,9 +451,14 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   const int last = num_stages(a) - 1;
   if (stage < 0 || stage > last) return hipErrorInvalidValue;
   if (a.algo == ALGO_FUSED && a.n_red_chunks > 0 && stage == last) {
-    hipLaunchKernelGGL(fast_reduce_kernel<InT>, dim3(a.grid_red_chunks), dim3(256), 0, st,
-                       a.insts, a.red_chunks, a.n_red_chunks, a.out_offset, a.partial,
-                       static_cast<InT*>(a.out));
+    if (a.red_rows == 1)
+      hipLaunchKernelGGL((fast_reduce_kernel<InT, 1>), dim3(a.grid_red_chunks), dim3(256), 0, st,
+                         a.insts, a.red_chunks, a.n_red_chunks, a.out_offset, a.partial,
+                         static_cast<InT*>(a.out));
+    else
+      hipLaunchKernelGGL((fast_reduce_kernel<InT, 4>), dim3(a.grid_red_chunks), dim3(256), 0, st,
+                         a.insts, a.red_chunks, a.n_red_chunks, a.out_offset, a.partial,
+                         static_cast<InT*>(a.out));
     return hipGetLastError();
   }
   if (a.algo == ALGO_FUSED && a.n_wide_items > 0) {
