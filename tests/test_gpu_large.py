@@ -1,14 +1,16 @@
-"""The operator at the largest sizes one MI355X holds in core (d = 26, 28, 30;
+"""The operator at the largest sizes one MI355X holds in core (d = 26 to 30;
 the paper's own method stops near d = 25 for memory). FP32 storage, on the
 register-phase kernel (at l = 4 past d = 20 with its outputs split into
-groups, each gathered by its own pass over the tiles).
+groups, each gathered by its own pass over the tiles) and, past its limits,
+on the generic kernel.
 
 d = 26 and 28: sampled outputs against the C oracle, which evaluates only the
 requested outputs (its Moebius transform still covers all 2^d values).
-d = 30: the oracle's 8 GiB FP64 Moebius is too slow for a test, so the check
-is a property that holds at any size: for a planted game (integer
-coefficients, so the FP32 input is exact) the result equals the unanimity
-closed form of Eq. 3 + Eq. 4 summed over the terms, and efficiency holds."""
+d = 29 and 30 (the largest sizes of each kernel and order): the oracle's
+FP64 Moebius at 4-8 GiB is too slow for a test, so the check is a property
+that holds at any size: for a planted game (integer coefficients, so the
+FP32 input is exact) the result equals the unanimity closed form of Eq. 3 +
+Eq. 4 summed over the terms, and efficiency holds."""
 import numpy as np
 import pytest
 
@@ -74,11 +76,26 @@ def _oracle_subset(v, d, l, W, masks):
     return E
 
 
-def test_d30_planted_closed_form():
-    d, l = 30, 2
+_PLANTED32 = {}
+
+
+def _planted32(d):
+    """FP32 values of the integer planted game at d (exact in FP32), kept
+    for the orders tested at the same d."""
+    if d not in _PLANTED32:
+        _PLANTED32.clear()
+        g = integer_planted(d, 16, 6, d)
+        _PLANTED32[d] = (g, games.planted_values(g).astype(np.float32))
+    return _PLANTED32[d]
+
+
+@pytest.mark.parametrize("d,l", [(29, 4), (30, 2), (30, 3), (30, 4)])
+def test_max_d_planted_closed_form(d, l):
+    """The largest instances: d = 29 at l = 4 (the register-phase kernel's
+    limit there, four output groups), d = 30 at l = 2, 3 (register-phase
+    kernel) and at l = 4 (generic kernel with the wide gather)."""
     say(f"[case] large d={d} l={l} FP32 planted, closed form")
-    g = integer_planted(d, 16, 6, 30)
-    v32 = games.planted_values(g).astype(np.float32)
+    g, v32 = _planted32(d)
     got = run(d, l, v32)
     want = P.fsi_sparse_mobius(zip(g.masks, g.coefs), d, l)
     assert normwise(got, want) < 1e-6
