@@ -184,15 +184,15 @@ struct EmitS1 {
 // counters i < RC (entries past this unit's range hold zeros), for the
 // prefixes with |sigma_A| + |sigma_B| <= L. Phase C reads only i <= 8 - |sigma_AB|,
 // all written here.
-template <typename SwT, int L, int SAMIN>
+template <typename SwT, int L, int SAMIN, int SAMAX>
 struct EmitS2 {
-  SwT* S2;   // offset by ((c / 4) * n3 + rankA) * 4 + c % 4
-  int sA;    // >= SAMIN
+  SwT* S2;   // offset by ((c / 4) * s2u + rankA) * 4 + c % 4
+  int sA;    // in [SAMIN, SAMAX]
   template <int SIG, int LO, int RC>
   __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
     constexpr int sB = cpop(SIG);
     if constexpr (sB <= L - SAMIN) {
-      if (sA <= L - sB) {
+      if (sB <= L - SAMAX || sA <= L - sB) {
         constexpr int UB = K<L>::ub.v[SIG];
         constexpr int S2U = K<L>::S2U;
 #pragma unroll
@@ -359,29 +359,32 @@ __device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, cons
   }
 }
 
-// Phase B of one wave: every sigma_A of the wave has |sigma_A| >= SAMIN, so
-// its counter rows past PA - SAMIN are zero and its leaves with |sigma_B| >
-// L - SAMIN are never written. HALF 0 walks the sigma = 0 subtree of the
-// first output site (all 16 inputs), HALF 1 the sigma = 1 subtree (the 8
-// tau = 1 inputs).
-constexpr int kSAHi = cpop(orderA(8));   // |sigma_A| of rank 8
-template <int L, int SAMIN, int HALF, typename SwT>
+// Phase B of one wave: every sigma_A of the wave has SAMIN <= |sigma_A| <=
+// SAMAX, so its counter rows past PA - SAMIN are zero and its leaves with
+// |sigma_B| > L - SAMIN are never written (both dropped at compile time),
+// while rows up to PA - SAMAX and leaves with |sigma_B| <= L - SAMAX need no
+// run-time test. HALF 0 walks the sigma = 0 subtree of the first output site
+// (all 16 inputs), HALF 1 the sigma = 1 subtree (the 8 tau = 1 inputs).
+constexpr int kSALoMax = cpop(orderA(7));   // |sigma_A| of rank 7
+constexpr int kSAHi = cpop(orderA(8));      // |sigma_A| of rank 8
+constexpr int kSAHiMax = cpop(orderA(15));  // |sigma_A| of rank 15
+template <int L, int SAMIN, int SAMAX, int HALF, typename SwT>
 __device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r, int p2c,
                                         const SwT* zrow) {
   if constexpr (SAMIN <= L) {
-    if (sA > L) return;
+    if (SAMAX > L && sA > L) return;
     using V = typename Vec4<SwT>::type;
     constexpr int VN = Vec4<SwT>::n;
     constexpr int H = NB / 2;
     constexpr int R1 = row1_stride<SwT>();
     constexpr int NRB = PA + 1 - SAMIN;
     constexpr int W = HALF == 0 ? NB : H;       // inputs this half reads
-    EmitS2<SwT, L, SAMIN> e2{S2w, sA};
+    EmitS2<SwT, L, SAMIN, SAMAX> e2{S2w, sA};
     const SwT* src0 = S1 + p2r * R1 + NB * p2c + (HALF == 0 ? 0 : H);
     SwT X[NRB][W];
 #pragma unroll
     for (int r = 0; r < NRB; ++r) {
-      if (r <= PA - sA) {
+      if (r <= PA - SAMAX || r <= PA - sA) {
         const V* src = reinterpret_cast<const V*>(src0 + K<L>::off1v.v[r] * R1);
 #pragma unroll
         for (int q = 0; q < W / VN; ++q) {
@@ -623,10 +626,10 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // subtree (which needs only the tau = 1 inputs); in each half the second
     // wave holds the sigma_A with |sigma_A| >= 2 ----
     switch (wave) {
-      case 0: phase_b<L, 0, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
-      case 1: phase_b<L, kSAHi, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
-      case 2: phase_b<L, 0, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
-      default: phase_b<L, kSAHi, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      case 0: phase_b<L, 0, kSALoMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      case 1: phase_b<L, kSAHi, kSAHiMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      case 2: phase_b<L, 0, kSALoMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      default: phase_b<L, kSAHi, kSAHiMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
     }
     __syncthreads();
     // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|,
