@@ -127,8 +127,19 @@ typedef struct {
   int32_t kernel;                /* fsi_kernel, default FSI_KERNEL_AUTO      */
   int32_t index;                 /* fsi_index, default FSI_INDEX_FSI         */
   int32_t input;                 /* fsi_input, default FSI_INPUT_VALUES      */
-  int32_t reserved[1];           /* must be 0                                */
+  int32_t allow_input_overwrite; /* 0 or 1, default 0; see below            */
 } fsi_plan_opts;
+
+/* allow_input_overwrite = 1 lets a two-pass plan (FSI_ALGO_TWO_PASS) run its
+ * Moebius butterfly in place on the input buffer instead of a workspace of
+ * 2^d elements per instance: no workspace is allocated, and after an apply
+ * the input buffer holds the Moebius transform a of v (Sec. 2.2; the same
+ * array fsi_mobius writes). It is honoured when the butterfly runs in the
+ * storage type (FSI_PREC_F64, FSI_PREC_F32); with a wider butterfly type
+ * (compensated, FP64 butterfly or FP64 sweep on FP32 storage) the plan keeps
+ * its workspace and leaves the input unmodified. The fused algorithm reads v
+ * once, never writes it and needs no such workspace, so it ignores the flag.
+ * Values other than 0 and 1 give FSI_ERR_INVALID_ARG. */
 
 /* Tile kernel of the fused algorithm. The register-phase kernel (tiles of
  * 11 low bits) covers every storage dtype and precision except
@@ -194,7 +205,8 @@ fsi_status fsi_plan_info(fsi_plan_t plan, int* tile_bits, int* block_threads,
                          int* algo, int* precision);
 
 /* out_dev[k] = E_{S_k} for the plan's (d, l); v_dev has 2^d elements and is
- * not modified; out_dev has M elements. Asynchronous on stream. */
+ * not modified (except by an in-place two-pass plan, see
+ * allow_input_overwrite); out_dev has M elements. Asynchronous on stream. */
 fsi_status fsi_apply(fsi_plan_t plan, const void* v_dev, void* out_dev,
                      hipStream_t stream);
 

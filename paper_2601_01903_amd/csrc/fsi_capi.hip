@@ -66,6 +66,7 @@ bool gfx950_device(int* dev, int* n_cu, std::string* why) { return device_is_gfx
 
 struct fsi_batch_plan_s {
   int n = 0, dtype = FSI_DTYPE_F64, prec = PREC_F64, algo = ALGO_FUSED;
+  int in_place = 0;                // two-pass: the input buffer is the Moebius workspace
   int device = 0, n_cu = 256;
   std::vector<int> d, l, cls_of;
   std::vector<int64_t> voff, ooff;
@@ -152,8 +153,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   fsi_plan_opts opts;
   fsi_default_opts(&opts);
   if (opts_in) opts = *opts_in;
-  for (int i = 0; i < 1; ++i)
-    if (opts.reserved[i] != 0) return fail(FSI_ERR_INVALID_ARG, "reserved option fields must be 0");
+  if (opts.allow_input_overwrite != 0 && opts.allow_input_overwrite != 1)
+    return fail(FSI_ERR_INVALID_ARG, "allow_input_overwrite must be 0 or 1");
   if (opts.input != FSI_INPUT_VALUES && opts.input != FSI_INPUT_MOBIUS)
     return fail(FSI_ERR_INVALID_ARG, "unknown input kind");
   if (opts.input == FSI_INPUT_MOBIUS && opts.algo == FSI_ALGO_TWO_PASS)
@@ -191,6 +192,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   auto* P = new (std::nothrow) fsi_batch_plan_s();
   if (!P) return fail(FSI_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->n = n; P->dtype = opts.dtype; P->prec = prec; P->algo = algo;
+  // the input buffer can hold the Moebius transform in place when the
+  // butterfly runs in the storage type
+  P->in_place = opts.allow_input_overwrite && algo == ALGO_TWO_PASS &&
+                mob_elem_bytes(prec) == (opts.dtype == FSI_DTYPE_F64 ? 8u : 4u);
   P->device = dev; P->n_cu = n_cu;
   P->d.assign(dh, dh + n);
   P->l.assign(lh, lh + n);
@@ -521,7 +526,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
 
   e = hipMalloc(reinterpret_cast<void**>(&P->Y), std::max<int64_t>(ytot, 1) * sizeof(double));
   if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(Y) failed"); }
-  if (algo == ALGO_TWO_PASS) {
+  if (algo == ALGO_TWO_PASS && !P->in_place) {
     const size_t wbytes = (size_t)wtot *
                           std::max(mob_elem_bytes(prec), (size_t)8);
     e = hipMalloc(&P->work, wbytes);
@@ -645,11 +650,19 @@ std::string tune_key(int n, const int* dh, const int* lh, const fsi_plan_opts& o
   return k;
 }
 
+// Launch arguments of one apply on the given buffers (an in-place two-pass
+// plan runs its Moebius passes on the input buffer).
+LaunchArgs apply_args(const fsi_batch_plan_s* P, const void* values, void* out) {
+  LaunchArgs a = P->args;
+  a.values = values;
+  a.out = out;
+  if (P->in_place) a.work = const_cast<void*>(values);
+  return a;
+}
+
 // Median device time of launch_apply over a few runs, in ms (< 0 on error).
 float time_plan(fsi_batch_plan_s* P, void* vin, void* vout, hipStream_t st) {
-  LaunchArgs a = P->args;
-  a.values = vin;
-  a.out = vout;
+  LaunchArgs a = apply_args(P, vin, vout);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return -1.f;
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.f; }
@@ -821,9 +834,7 @@ fsi_status fsi_apply(fsi_plan_t plan, const void* v_dev, void* out_dev, hipStrea
   fsi_status st;
   if ((st = check_ptr(v_dev, "v_dev")) != FSI_OK) return st;
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
-  LaunchArgs a = plan->bp->args;
-  a.values = v_dev;
-  a.out = out_dev;
+  LaunchArgs a = apply_args(plan->bp, v_dev, out_dev);
   HIP_TRY(launch_apply(a, stream));
   return FSI_OK;
 }
@@ -868,9 +879,7 @@ fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan, const void* values_d
   fsi_status st;
   if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
-  LaunchArgs a = plan->args;
-  a.values = values_dev;
-  a.out = out_dev;
+  LaunchArgs a = apply_args(plan, values_dev, out_dev);
   HIP_TRY(launch_apply(a, stream));
   return FSI_OK;
 }
@@ -885,9 +894,7 @@ fsi_status fsi_apply_batched(fsi_batch_plan_t plan, const void* values_dev, void
     if (plan->exec) { HIP_TRY(hipGraphExecDestroy(plan->exec)); plan->exec = nullptr; }
     if (plan->graph) { HIP_TRY(hipGraphDestroy(plan->graph)); plan->graph = nullptr; }
     if (!plan->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
-    LaunchArgs a = plan->args;
-    a.values = values_dev;
-    a.out = out_dev;
+    LaunchArgs a = apply_args(plan, values_dev, out_dev);
     HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_apply(a, plan->cap_stream);
     hipGraph_t g = nullptr;
@@ -919,9 +926,7 @@ fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
   if (stage < 0 || stage >= num_stages(plan->args))
     return fail(FSI_ERR_INVALID_ARG, "stage out of range");
-  LaunchArgs a = plan->args;
-  a.values = values_dev;
-  a.out = out_dev;
+  LaunchArgs a = apply_args(plan, values_dev, out_dev);
   HIP_TRY(launch_stage(a, stage, stream));
   return FSI_OK;
 }

@@ -48,7 +48,7 @@ class Opts(ctypes.Structure):
                 ("algo", ctypes.c_int32), ("tile_bits", ctypes.c_int32),
                 ("block_threads", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("kernel", ctypes.c_int32), ("index", ctypes.c_int32),
-                ("input", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("input", ctypes.c_int32), ("allow_input_overwrite", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -124,7 +124,7 @@ def num_outputs(d: int, l: int) -> int:
 
 def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
               block_threads=0, kernel="auto", autotune=False, index="fsi",
-              input="values") -> Opts:
+              input="values", allow_input_overwrite=False) -> Opts:
     o = Opts()
     _check(load().fsi_default_opts(ctypes.byref(o)), "fsi_default_opts")
     o.dtype = DTYPES[dtype]
@@ -136,6 +136,7 @@ def make_opts(dtype="f64", precision="auto", algo="auto", tile_bits=0,
     o.autotune = 1 if autotune else 0
     o.index = INDICES[index]
     o.input = INPUTS[input]
+    o.allow_input_overwrite = 1 if allow_input_overwrite else 0
     return o
 
 
@@ -163,12 +164,12 @@ class Plan:
     def __init__(self, d: int, l: int, dtype: str = "f64", precision: str = "auto",
                  algo: str = "auto", tile_bits: int = 0, block_threads: int = 0,
                  kernel: str = "auto", autotune: bool = False, index: str = "fsi",
-                 input: str = "values"):
+                 input: str = "values", allow_input_overwrite: bool = False):
         lib = load()
         self.d, self.l, self.dtype, self.index = d, l, dtype, index
         self._h = ctypes.c_void_p()
         opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel, autotune,
-                         index, input)
+                         index, input, allow_input_overwrite)
         _check(lib.fsi_plan_ex(d, l, ctypes.byref(opts), ctypes.byref(self._h)), "fsi_plan_ex")
         self.M = num_outputs(d, l)
 
@@ -227,7 +228,8 @@ class BatchPlan:
     def __init__(self, ds: Sequence[int], ls: Sequence[int], dtype: str = "f32",
                  precision: str = "auto", algo: str = "auto", tile_bits: int = 0,
                  block_threads: int = 0, kernel: str = "auto", autotune: bool = False,
-                 index: str = "fsi", input: str = "values"):
+                 index: str = "fsi", input: str = "values",
+                 allow_input_overwrite: bool = False):
         lib = load()
         n = len(ds)
         if len(ls) != n:
@@ -237,7 +239,7 @@ class BatchPlan:
         darr = (ctypes.c_int * n)(*ds)
         larr = (ctypes.c_int * n)(*ls)
         opts = make_opts(dtype, precision, algo, tile_bits, block_threads, kernel, autotune,
-                         index, input)
+                         index, input, allow_input_overwrite)
         self._h = ctypes.c_void_p()
         _check(lib.fsi_plan_batched(n, darr, larr, ctypes.byref(opts), ctypes.byref(self._h)),
                "fsi_plan_batched")

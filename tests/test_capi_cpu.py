@@ -59,6 +59,10 @@ def test_invalid_arguments_rejected_before_device_use():
     assert lib.fsi_plan_batched(2, darr, larr, None, ctypes.byref(h)) == 1
     assert lib.fsi_plan_batched(0, darr, larr, None, ctypes.byref(h)) == 1
     assert lib.fsi_apply(None, None, None, None) == 1
+    o = fsi.make_opts(algo="two_pass")
+    o.allow_input_overwrite = 2
+    assert lib.fsi_plan_ex(10, 2, ctypes.byref(o), ctypes.byref(h)) == 1
+    assert b"allow_input_overwrite" in lib.fsi_last_error()
     assert lib.fsi_plan_destroy(None) == 0
     assert lib.fsi_batch_plan_destroy(None) == 0
 
