@@ -350,12 +350,19 @@ def main():
     log(f"FP32 batched, graph replay: {graph_ms:.3f} ms/step")
 
     # ---- copy-kernel calibration for the HBM byte counters: a plain
-    # device-to-device copy of the FP32 input (known size) ----
+    # device-to-device copy of the FP32 input (known size); also timed, as the
+    # bandwidth a plain streaming kernel reaches on this device ----
     cal = torch.empty_like(x32)
-    for _ in range(3):
+    cev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    cev[0].record(stream)
+    for i in range(3):
         cal.copy_(x32)
+        cev[i + 1].record(stream)
     torch.cuda.synchronize()
     del cal
+    copy_ms = float(np.median([cev[i].elapsed_time(cev[i + 1]) for i in range(3)]))
+    copy_gbs = 2 * alg_bytes / (copy_ms * 1e-3) / 1e9   # read + write
+    log(f"device-to-device copy of the input: {copy_ms:.3f} ms = {copy_gbs:.0f} GB/s (read + write)")
     res32 = out32.double().cpu().numpy()
 
     # ---- the other interaction indices through the same kernels: same
@@ -546,6 +553,9 @@ def main():
                      "traffic_unit": "HBM bytes per launch",
                      "algorithmic_bytes": alg_bytes,
                      "kernel": f"stage {dom} of {ns}", "kernel_ms": stage_ms[dom]},
+        "copy_bandwidth": {"gbs": copy_gbs, "ms": copy_ms, "bytes": 2 * alg_bytes,
+                           "what": "torch copy_ of the 1 GiB FP32 input, device to device (read + write)",
+                           "tile_kernel_frac_of_copy": achieved / copy_gbs},
         "stage_ms": stage_ms,
         "graph_replay_ms_per_step": graph_ms,
         "schedule": sched,
