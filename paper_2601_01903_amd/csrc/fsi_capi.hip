@@ -501,7 +501,6 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     const FastClassHost& F = P->fclasses[f];
     FastClassDev& D = fdev[f];
     D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk; D.mshift = F.mshift;
-    D.mobius_in = F.mobius_in;
     fast_lds[F.l] = fast_lds_bytes(prec, F.l);
     fast_lds_max = std::max(fast_lds_max, fast_lds[F.l]);
     D.lam = reinterpret_cast<const double*>(A + fo[f].lam);

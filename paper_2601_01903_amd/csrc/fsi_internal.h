@@ -47,8 +47,7 @@ struct FastClassDev {
   int32_t d, l, h, M;
   int32_t nkk;                // slots per thread in use (largest over the output groups)
   int32_t mshift;             // bits of the Y byte offset in a metadata word
-  int32_t mobius_in;          // 1: the input is already the Moebius transform
-  int32_t pad0;
+  int32_t pad0, pad1;
   const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
   const uint32_t* meta;       // [groups * 256 * kFastMetaStride] per group and thread:
                               // Y byte offset | S_H << mshift
@@ -56,7 +55,7 @@ struct FastClassDev {
   const int32_t* gnkk;        // [groups] slots per thread in use in each output group
   const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
   const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
-  const int32_t* uperm;       // [256] phase-C unit of thread t (units by |sigma_AB|)
+  const int32_t* uperm;       // [256] phase-C unit of thread t, -1 for none (heavy units on two lanes)
 };
 
 struct FastClassHost {
