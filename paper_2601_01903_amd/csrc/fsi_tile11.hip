@@ -479,6 +479,22 @@ __device__ __forceinline__ void phase_c(const SwT* S2, SwT* Z, const int (&zr)[N
   }
 }
 
+// ---------------------------------------------------------- wave priority
+// Two workgroups share each SIMD (one wave of each). Within a step separated
+// by barriers the waves' shares of the work differ; the wave with the
+// longest share is issued first (s_setprio), so the other workgroup's waves
+// fill the idle cycles instead of delaying that step's slowest wave.
+template <int P> __device__ __forceinline__ void wave_prio() { __builtin_amdgcn_s_setprio(P); }
+// phase B: (half 0, low |sigma_A|) > (half 0, high) > (half 1, low) > (half 1, high)
+constexpr int kPrioB[NT / 64] = {3, 2, 1, 0};
+// phase C: heavy sigma = 0 subtrees > low-|sigma_AB| whole trees > heavy
+// sigma = 1 subtrees > the rest
+constexpr int prio_c(int w) {
+  return w == kCWaveH0 ? 3 : w == kCWaveR0 ? 2 : w == kCWaveH1 ? 1 : 0;
+}
+// the two-wave Moebius steps run ahead of the idle waves' next step
+constexpr int kPrioTwoWave = 1;
+
 // ------------------------------------------------------------------ item
 template <int L, typename SwT, typename MobT, bool IN64, bool GROUPED, bool MOBIN>
 __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, const InstDev& I,
@@ -582,6 +598,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     __syncthreads();
     // ---- Moebius over bits 4-7: thread (a, c) holds the 16 b values ----
     if (tid < NA * NC) {
+      wave_prio<kPrioTwoWave>();
       MobT* rp = R + (tid & 15) + RC_ * (tid >> 4);
       MobT y[NB];
 #pragma unroll
@@ -595,12 +612,14 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) rp[RB * b] = y[b];
+      wave_prio<0>();
     }
     __syncthreads();
     // ---- Moebius over bits 0-3 + phase A: thread (b, c) of waves 2-3 holds
     // the 16 a values (waves 0-1 ran the B bits: the two-wave steps are
     // spread over all four SIMDs) ----
     if (tid >= NT - NB * NC) {
+      wave_prio<kPrioTwoWave>();
       const int ta = tid - (NT - NB * NC);
       const MobT* rp = R + RB * (ta & 15) + RC_ * (ta >> 4);
       MobT y[NA];
@@ -618,6 +637,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       for (int a = 0; a < NA; ++a) X1[0][a] = to_sw<SwT>(y[a]);
       EmitS1<SwT, L> e1{S1 + ta};
       rsweep<PA, 0, 1, 0>(X1, e1);
+      wave_prio<0>();
     }
     __syncthreads();
     // ---- phase B: thread (half, sigma_A, c), counters relative to |sigma_A|;
@@ -626,11 +646,24 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // subtree (which needs only the tau = 1 inputs); in each half the second
     // wave holds the sigma_A with |sigma_A| >= 2 ----
     switch (wave) {
-      case 0: phase_b<L, 0, kSALoMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
-      case 1: phase_b<L, kSAHi, kSAHiMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
-      case 2: phase_b<L, 0, kSALoMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
-      default: phase_b<L, kSAHi, kSAHiMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow); break;
+      case 0:
+        wave_prio<kPrioB[0]>();
+        phase_b<L, 0, kSALoMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        break;
+      case 1:
+        wave_prio<kPrioB[1]>();
+        phase_b<L, kSAHi, kSAHiMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        break;
+      case 2:
+        wave_prio<kPrioB[2]>();
+        phase_b<L, 0, kSALoMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        break;
+      default:
+        wave_prio<kPrioB[3]>();
+        phase_b<L, kSAHi, kSAHiMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        break;
     }
+    wave_prio<0>();
     __syncthreads();
     // ---- phase C: thread per unit sigma_AB (units in order of |sigma_AB|,
     // the heavy ones split between two waves), counters relative to
@@ -638,11 +671,24 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     if (c_on) {
       using O = UO<L>;
       switch (wave) {
-        case 0: phase_c<L, O::o.kmin[0], O::o.kmax[0], O::o.part[0], SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        case 1: phase_c<L, O::o.kmin[1], O::o.kmax[1], O::o.part[1], SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        case 2: phase_c<L, O::o.kmin[2], O::o.kmax[2], O::o.part[2], SwT>(S2, Z, zr, sAB, u3, zrow); break;
-        default: phase_c<L, O::o.kmin[3], O::o.kmax[3], O::o.part[3], SwT>(S2, Z, zr, sAB, u3, zrow); break;
+        case 0:
+          wave_prio<prio_c(0)>();
+          phase_c<L, O::o.kmin[0], O::o.kmax[0], O::o.part[0], SwT>(S2, Z, zr, sAB, u3, zrow);
+          break;
+        case 1:
+          wave_prio<prio_c(1)>();
+          phase_c<L, O::o.kmin[1], O::o.kmax[1], O::o.part[1], SwT>(S2, Z, zr, sAB, u3, zrow);
+          break;
+        case 2:
+          wave_prio<prio_c(2)>();
+          phase_c<L, O::o.kmin[2], O::o.kmax[2], O::o.part[2], SwT>(S2, Z, zr, sAB, u3, zrow);
+          break;
+        default:
+          wave_prio<prio_c(3)>();
+          phase_c<L, O::o.kmin[3], O::o.kmax[3], O::o.part[3], SwT>(S2, Z, zr, sAB, u3, zrow);
+          break;
       }
+      wave_prio<0>();
     }
     // prefetch the next tile and this tile's output metadata while the
     // weight core runs
