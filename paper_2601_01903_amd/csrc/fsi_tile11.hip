@@ -492,7 +492,9 @@ constexpr int kPrioB[NT / 64] = {3, 2, 1, 0};
 constexpr int prio_c(int w) {
   return w == kCWaveH0 ? 3 : w == kCWaveR0 ? 2 : w == kCWaveH1 ? 1 : 0;
 }
-// the two-wave Moebius steps run ahead of the idle waves' next step
+// the two-wave Moebius steps run ahead of the idle waves' next step; the
+// weight core and the gather (every wave an equal share) stay at 0, behind
+// the sweep steps of the other workgroup
 constexpr int kPrioTwoWave = 1;
 
 // ------------------------------------------------------------------ item
@@ -576,7 +578,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       u_prev = u;
     }
 
-    // ---- Moebius over bits 8-10 in registers, then transpose ----
+    // ---- Moebius over bits 8-10 in registers, then transpose (ahead of
+    // the other workgroup's weight core and gather) ----
+    wave_prio<1>();
     MobT xr[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -595,6 +599,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
 #pragma unroll
       for (int c = 0; c < NC; ++c) rp[RC_ * c] = xr[c];
     }
+    wave_prio<0>();
     __syncthreads();
     // ---- Moebius over bits 4-7: thread (a, c) holds the 16 b values ----
     if (tid < NA * NC) {
