@@ -31,7 +31,9 @@
 // Every LDS layout is a compile-time function of l (fsi_tile11.h), so the
 // hot loops address LDS with one per-thread base register and immediate
 // offsets. LDS regions:
-//   region 1: raw-tile transposes -> phase-B states S2 -> partial results Y
+//   region 1: raw-tile transposes and, after them, the partial results Y;
+//             phase-B states S2 overlay both (no barrier between a tile's
+//             gather and the next tile's loads)
 //   region 2: phase-A states S1 -> final states Z
 //   region 3: the final-core weights of the current |U_H|
 //   a zero row read in place of counter rows past a unit's range
@@ -234,8 +236,12 @@ constexpr int align256(int x) { return (x + 255) & ~255; }
 constexpr int imax2(int a, int b) { return a > b ? a : b; }
 template <int L, typename SwT, typename MobT>
 struct Lds {
-  static constexpr int reg1 = align256(imax2(
-      imax2((int)(s2_elems(L) * sizeof(SwT)), (int)(r_elems * sizeof(MobT))), ysize(L) * 8));
+  // region 1: the raw-tile transposes at 0 and the partial results Y after
+  // them (disjoint, so the next tile's loads and first transpose may start
+  // while slower waves still gather this tile's Y); phase B's states S2
+  // overlay both
+  static constexpr int yoff = align256((int)(r_elems * sizeof(MobT)));
+  static constexpr int reg1 = align256(imax2((int)(s2_elems(L) * sizeof(SwT)), yoff + ysize(L) * 8));
   static constexpr int reg2 = align256(
       imax2(rows1(L) * row1_stride<SwT>() * (int)sizeof(SwT),
             (nzrows(L) + 1) * ZROW * (int)sizeof(SwT)));
@@ -509,7 +515,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   using LD = Lds<L, SwT, MobT>;
   MobT* R = reinterpret_cast<MobT*>(smem);
   SwT* S2 = reinterpret_cast<SwT*>(smem);
-  double* Y = reinterpret_cast<double*>(smem);
+  double* Y = reinterpret_cast<double*>(smem + LD::yoff);
   SwT* S1 = reinterpret_cast<SwT*>(smem + LD::reg1);
   SwT* Z = reinterpret_cast<SwT*>(smem + LD::reg1);
   double* lamL = reinterpret_cast<double*>(smem + LD::reg1 + LD::reg2);
@@ -736,7 +742,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
       }
     }
     UH = UHn;
-    __syncthreads();
+    // no barrier: the next tile's first writes (the transpose region, and
+    // the weights once every wave has passed the barrier before this
+    // gather) do not touch Y
   }
   double* P = partial + W.pofs + tid;
 #pragma unroll
