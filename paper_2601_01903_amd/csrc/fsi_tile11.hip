@@ -375,8 +375,7 @@ constexpr int kSALoMax = cpop(orderA(7));   // |sigma_A| of rank 7
 constexpr int kSAHi = cpop(orderA(8));      // |sigma_A| of rank 8
 constexpr int kSAHiMax = cpop(orderA(15));  // |sigma_A| of rank 15
 template <int L, int SAMIN, int SAMAX, int HALF, typename SwT>
-__device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r, int p2c,
-                                        const SwT* zrow) {
+__device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r, int p2c) {
   if constexpr (SAMIN <= L) {
     if (SAMAX > L && sA > L) return;
     using V = typename Vec4<SwT>::type;
@@ -659,19 +658,19 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     switch (wave) {
       case 0:
         wave_prio<kPrioB[0]>();
-        phase_b<L, 0, kSALoMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        phase_b<L, 0, kSALoMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c);
         break;
       case 1:
         wave_prio<kPrioB[1]>();
-        phase_b<L, kSAHi, kSAHiMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        phase_b<L, kSAHi, kSAHiMax, 0, SwT>(S1, S2 + wb, sA, p2r, p2c);
         break;
       case 2:
         wave_prio<kPrioB[2]>();
-        phase_b<L, 0, kSALoMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        phase_b<L, 0, kSALoMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c);
         break;
       default:
         wave_prio<kPrioB[3]>();
-        phase_b<L, kSAHi, kSAHiMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c, zrow);
+        phase_b<L, kSAHi, kSAHiMax, 1, SwT>(S1, S2 + wb, sA, p2r, p2c);
         break;
     }
     wave_prio<0>();
