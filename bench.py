@@ -273,8 +273,8 @@ def main():
                     help="use the heuristic schedule instead of timing candidates at plan time")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the batched operator shards by instance across GPUs, which is not built here.",
+        print(f"bench.py: the library runs on one GPU (asked for --gpus {args.gpus}); "
+              "sharding the batched operator by instance across GPUs is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
