@@ -9,10 +9,11 @@
  *
  * with a the Moebius transform of v (Sec. 2.2, Eq. 3 and Eq. 4; Sec. 4.1,
  * Eq. 5) and w the cardinality-only weight of Sec. 4.3, Eq. 7. The GPU
- * computes it as a Moebius butterfly (Sec. 3.2) followed by the left-to-right
- * MPO sweep over (|S|, |T|) counter states (Sec. 4.3 - 4.4, Algorithm 1),
- * with the Moebius cores of the high sites precontracted into the final
- * weight core (Sec. 4.5) in the fused algorithm.
+ * computes it as a Moebius butterfly (Sec. 4.2, the Moebius transform as a
+ * rank-1 MPO; Appendix B) followed by the left-to-right MPO sweep over
+ * (|S|, |T|) counter states (Sec. 4.3 - 4.4, Algorithm 1), with the Moebius
+ * cores of the high sites precontracted into the final weight core
+ * (Sec. 4.5) in the fused algorithm.
  *
  * Conventions (all entry points):
  *  - v is indexed by a d-bit mask: bit i set <=> player i in the coalition.
@@ -29,8 +30,14 @@
  *  - A plan owns its device tables and workspace; it is immutable after
  *    creation. Concurrent applies of ONE plan on different streams race on
  *    its workspace; use one plan per stream.
- *  - No C++ exception crosses this ABI. Every non-OK status sets a
+ *  - No C++ exception crosses this ABI: a failed host allocation returns
+ *    FSI_ERR_OUT_OF_MEMORY, any other internal exception FSI_ERR_INTERNAL,
+ *    and the partly built object is freed. Every non-OK status sets a
  *    thread-local message readable with fsi_last_error().
+ *  - Test hook: with the environment variable FSI_TEST_FAIL_ALLOC=host a
+ *    plan's host-table allocation fails (std::bad_alloc, before any device
+ *    call), with FSI_TEST_FAIL_ALLOC=device its device workspace allocation
+ *    fails; both return FSI_ERR_OUT_OF_MEMORY and free what was built.
  */
 #ifndef FSI_MI355X_H
 #define FSI_MI355X_H
@@ -63,10 +70,12 @@ typedef enum {
   FSI_PREC_F32_FP64MOB = 3,     /* FP64 Moebius, FP32 sweep                 */
   FSI_PREC_F32_FP64REG = 4,     /* FP32 storage, FP64 Moebius and sweep     */
   FSI_PREC_AUTO = 5             /* F64 for FP64 storage; F32_FP64MOB for    */
-                                /* FP32 storage (on gfx950 FP64 runs at     */
-                                /* half the FP32 rate, so the FP64          */
-                                /* butterfly is cheaper than the two-float  */
-                                /* one and at least as accurate)            */
+                                /* FP32 storage (on gfx950 an FP64 add      */
+                                /* issues at the rate of an unpacked FP32   */
+                                /* add, so the FP64 butterfly costs one     */
+                                /* instruction per step against about eight */
+                                /* for the two-float one, and is at least   */
+                                /* as accurate)                             */
 } fsi_precision;
 
 typedef enum {
@@ -121,7 +130,8 @@ typedef struct {
   int32_t precision;             /* fsi_precision, default FSI_PREC_AUTO     */
   int32_t algo;                  /* fsi_algo, default FSI_ALGO_AUTO          */
   int32_t tile_bits;             /* b, 0 = choose (autotuned if enabled)     */
-  int32_t block_threads;         /* workgroup size, 0 = choose               */
+  int32_t block_threads;         /* reserved, must be 0: each kernel has a   */
+                                 /* fixed workgroup size (fsi_plan_info)    */
   int32_t autotune;              /* 1 = time candidate schedules at plan     */
                                  /* time (see fsi_schedule), keep the best   */
   int32_t kernel;                /* fsi_kernel, default FSI_KERNEL_AUTO      */
@@ -180,37 +190,48 @@ typedef struct {
 /* Fill opts with the defaults listed above. */
 fsi_status fsi_default_opts(fsi_plan_opts* opts);
 
-/* M(d, l) = sum_{s=0..l} C(d, s): number of outputs (the empty set counts),
- * or -1 if not 1 <= l <= d <= 30. */
+/* M(d, l) = sum_{s=0..l} C(d, s): number of outputs, one per coalition S with
+ * |S| <= l (the output set of Eq. 3, Sec. 2.2; the empty set counts), or -1
+ * if not 1 <= l <= d <= 30. Host only. */
 int64_t fsi_num_outputs(int d, int l);
 
-/* Plan for one instance size. Requires 1 <= d <= 30 and 1 <= l <= d
- * (else FSI_ERR_INVALID_ARG; l = 0 is rejected). Uses the current HIP device,
- * which must be gfx950 (else FSI_ERR_UNSUPPORTED). fsi_plan uses FP64
- * storage and defaults. *out receives the plan (NULL on failure). */
+/* Plan for one instance size of the operator of Sec. 4.1, Eq. 5 (Eq. 3 - 4
+ * with the weights of Eq. 7, Sec. 4.3): the exact weight tables, the sweep's
+ * counter-state tables and the launch schedule. Requires 1 <= d <= 30 and
+ * 1 <= l <= d (else FSI_ERR_INVALID_ARG; l = 0 is rejected). Uses the
+ * current HIP device, which must be gfx950 (else FSI_ERR_UNSUPPORTED).
+ * fsi_plan uses FP64 storage and defaults. *out receives the plan (NULL on
+ * failure); the caller destroys it with fsi_plan_destroy. */
 fsi_status fsi_plan(int d, int l, fsi_plan_t* out);
 fsi_status fsi_plan_ex(int d, int l, const fsi_plan_opts* opts, fsi_plan_t* out);
 
 /* Frees the plan's host tables, device tables and workspace. NULL is a
- * no-op. Waits for the plan's in-flight work on the device first. */
+ * no-op. Waits first for the plan's work issued by the apply calls (an
+ * event recorded on the apply's stream after each call, outside stream
+ * capture), not for the whole device. */
 fsi_status fsi_plan_destroy(fsi_plan_t plan);
 
-/* Writes the M output masks of the plan, in canonical order, to host_masks
- * (caller-owned, length fsi_num_outputs(d, l)). */
+/* Writes the M output masks of the plan (the coalitions S, |S| <= l, of
+ * Eq. 3, Sec. 2.2), in canonical order, to host_masks (caller-owned host
+ * memory, length fsi_num_outputs(d, l)). Host only. */
 fsi_status fsi_output_masks(fsi_plan_t plan, uint32_t* host_masks);
 
-/* Schedule actually chosen (tile bits b, workgroup size, algorithm,
- * precision), for reporting. Any pointer may be NULL. */
+/* Schedule actually chosen, for reporting: tile bits b, the workgroup size
+ * of the plan's tile kernel (256 on the register-phase kernel, 512 on the
+ * generic one), algorithm, precision. Any pointer may be NULL. */
 fsi_status fsi_plan_info(fsi_plan_t plan, int* tile_bits, int* block_threads,
                          int* algo, int* precision);
 
-/* out_dev[k] = E_{S_k} for the plan's (d, l); v_dev has 2^d elements and is
- * not modified (except by an in-place two-pass plan, see
- * allow_input_overwrite); out_dev has M elements. Asynchronous on stream. */
+/* out_dev[k] = E_{S_k} for the plan's (d, l): the operator of Sec. 4.1,
+ * Eq. 5 (Moebius transform, then the correction of Eq. 4 with the weights
+ * of Eq. 7). v_dev has 2^d elements and is not modified (except by an
+ * in-place two-pass plan, see allow_input_overwrite); out_dev has M
+ * elements; both are caller-owned device memory in the storage dtype.
+ * Asynchronous on stream. */
 fsi_status fsi_apply(fsi_plan_t plan, const void* v_dev, void* out_dev,
                      hipStream_t stream);
 
-/* Moebius transform alone (Sec. 3.2, Appendix B), in place on a_dev
+/* Moebius transform alone (Sec. 4.2, Appendix B), in place on a_dev
  * (2^d elements of the plan's storage dtype): for every bit i and every mask
  * m with bit i set, a[m] -= a[m with bit i cleared]. Low bits are staged in
  * LDS, high bits run as coalesced strided passes. */
@@ -245,10 +266,16 @@ fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan,
                                      const void* values_dev, void* out_dev,
                                      hipStream_t stream);
 
-/* The kernel launches of one batched apply, for per-kernel timing: the
- * fused algorithm has 2 stages (tile kernel: in-tile Moebius + counter sweep
- * + final weights; then the cross-tile reduction), the two-pass algorithm
- * has 3 + (number of strided high-bit Moebius passes). Running stages
+
+/* The kernel launches of one batched apply, for per-kernel timing. The
+ * fused algorithm launches, in this order and each only if the plan has
+ * such work: the register-phase tile kernel once per order l present
+ * (in-tile Moebius + counter sweep + final weights + cross-tile sums per
+ * work item), the generic tile kernel, the generic per-output reduction,
+ * the wide gather and its final pass (generic instances with at least 2^10
+ * tiles), and the reduction of the register-phase partial sums. The
+ * two-pass algorithm has 3 + (number of strided high-bit Moebius passes)
+ * stages (low pass, high passes, tile kernel, reduction). Running stages
  * 0 .. n-1 in order on one stream equals fsi_apply_batched_nograph.
  * fsi_batch_num_stages returns -1 for a NULL plan. */
 int fsi_batch_num_stages(fsi_batch_plan_t plan);

@@ -86,7 +86,7 @@ def weight_table_f64(d: int, l: int) -> np.ndarray:
 
 
 def mobius(v: np.ndarray) -> np.ndarray:
-    """Moebius transform a = mu_down v (Sec. 3.2 and Appendix B: mu_down is the
+    """Moebius transform a = mu_down v (Sec. 4.2 and Appendix B: mu_down is the
     Kronecker product of the 2x2 factors [[1, 0], [-1, 1]]), applied one bit
     axis at a time: for every mask m with bit i set, a[m] -= a[m without i]."""
     a = np.array(v, dtype=np.float64, copy=True)

@@ -21,7 +21,7 @@
 #include <omp.h>
 #endif
 
-/* In-place Moebius butterfly over all d bit axes (Sec. 3.2 / Appendix B). */
+/* In-place Moebius butterfly over all d bit axes (Sec. 4.2 / Appendix B). */
 void oracle_mobius(double *a, int d)
 {
     const int64_t n = (int64_t)1 << d;

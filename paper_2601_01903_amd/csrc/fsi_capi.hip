@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "../../include/fsi.h"
+#include "fsi_abi.h"
 #include "fsi_internal.h"
 #include "fsi_kernels.h"
 
@@ -61,6 +63,22 @@ bool device_is_gfx950(int* dev, int* n_cu, std::string* why) {
 
 namespace fsi {
 void record_error(const std::string& msg) { g_err = msg; }
+void record_error_noexcept(const char* msg) noexcept {
+  try {
+    g_err = msg;
+  } catch (...) {
+  }
+}
+void record_error_noexcept2(const char* a, const char* b) noexcept {
+  try {
+    g_err = std::string(a) + b;
+  } catch (...) {
+  }
+}
+bool test_fail_alloc(const char* site) {
+  const char* v = std::getenv("FSI_TEST_FAIL_ALLOC");
+  return v && std::strcmp(v, site) == 0;
+}
 bool gfx950_device(int* dev, int* n_cu, std::string* why) { return device_is_gfx950(dev, n_cu, why); }
 }  // namespace fsi
 
@@ -80,6 +98,13 @@ struct fsi_batch_plan_s {
   std::vector<FastClassHost> fclasses;
   std::vector<int> fast_of;        // per class: index into fclasses or -1
   LaunchArgs args{};
+  // bytes of each device workspace an apply writes and reads back (partial
+  // sums, per-tile results, wide-gather partials, two-pass Moebius
+  // workspace)
+  size_t partial_bytes = 0, y_bytes = 0, wide_bytes = 0, work_bytes = 0;
+  // recorded after every apply on the caller's stream (outside stream
+  // capture): destroying the plan waits for it, not for the whole device
+  hipEvent_t done = nullptr;
   int tile_bits_reported = 0;
   fsi_schedule sched{};            // the schedule this plan was built with
   // graph cache
@@ -100,7 +125,14 @@ namespace {
 
 void free_batch(fsi_batch_plan_s* p) {
   if (!p) return;
-  (void)hipDeviceSynchronize();
+  if (p->done) {
+    (void)hipEventSynchronize(p->done);
+    (void)hipEventDestroy(p->done);
+  }
+  // an apply still replaying on the plan's capture stream, or a launch on a
+  // stream the completion event did not see (one being captured by the
+  // caller): the plan's own stream and the kernels it replayed finish first
+  if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
@@ -175,8 +207,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   if (opts.algo < 0 || opts.algo > FSI_ALGO_TWO_PASS)
     return fail(FSI_ERR_INVALID_ARG, "unknown algo");
   const int algo = opts.algo == FSI_ALGO_AUTO ? ALGO_FUSED : opts.algo;
-  if (opts.block_threads != 0 && opts.block_threads != kTileThreads)
-    return fail(FSI_ERR_UNSUPPORTED, "block_threads must be 0 or 512");
+  if (opts.block_threads != 0)
+    return fail(FSI_ERR_INVALID_ARG, "block_threads is reserved and must be 0");
   if (opts.tile_bits < 0 || opts.tile_bits > kMaxTileBits)
     return fail(FSI_ERR_INVALID_ARG, "tile_bits must be in [0, 12]");
   for (int i = 0; i < n; ++i) {
@@ -185,12 +217,20 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     if (opts.tile_bits > dh[i])
       return fail(FSI_ERR_INVALID_ARG, "tile_bits larger than d");
   }
+  // test hook: a host allocation failure while the plan is built (before
+  // any device call, so it is reachable without a GPU)
+  if (test_fail_alloc("host")) throw std::bad_alloc();
   int dev = 0, n_cu = 0;
   std::string why;
   if (!device_is_gfx950(&dev, &n_cu, &why)) return fail(FSI_ERR_UNSUPPORTED, why);
 
   auto* P = new (std::nothrow) fsi_batch_plan_s();
   if (!P) return fail(FSI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  // frees the partly built plan if a host allocation below throws
+  struct Guard {
+    fsi_batch_plan_s* p;
+    ~Guard() { free_batch(p); }
+  } guard{P};
   P->n = n; P->dtype = opts.dtype; P->prec = prec; P->algo = algo;
   // the input buffer can hold the Moebius transform in place when the
   // butterfly runs in the storage type
@@ -218,25 +258,23 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
                              fast_output_slots(dh[i], lh[i]) >= 0 &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
       if (kern == FSI_KERNEL_REGISTER && !want_fast) {
-        free_batch(P);
         return fail(FSI_ERR_UNSUPPORTED, "register-phase kernel does not apply to instance " +
                                              std::to_string(i));
       }
       int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
       if (!want_fast && opts.tile_bits == 0) b = std::max(1, b + sc.tb_shift);
       std::string err = build_class(dh[i], lh[i], b, algo, opts.index, opts.input, &C);
-      if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
+      if (!err.empty()) { return fail(FSI_ERR_INTERNAL, err); }
       const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
                                              ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));
       if (!want_fast && need > kLdsBudget) {
-        free_batch(P);
         return fail(FSI_ERR_INVALID_ARG, "tile_bits too large for LDS at this l and precision");
       }
       int fidx = -1;
       if (want_fast) {
         FastClassHost F;
         err = build_fast_class(C, &F);
-        if (!err.empty()) { free_batch(P); return fail(FSI_ERR_INTERNAL, err); }
+        if (!err.empty()) { return fail(FSI_ERR_INTERNAL, err); }
         fidx = (int)P->fclasses.size();
         P->fclasses.push_back(std::move(F));
       }
@@ -334,7 +372,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     fpidx[f].resize(F.pidx.size());
     for (size_t k = 0; k < F.pidx.size(); ++k) {
       const int64_t pos = (int64_t)F.pgroup[k] * nr * pstride + F.pidx[k];
-      if (pos >= ((int64_t)1 << 31)) { free_batch(P); return fail(FSI_ERR_INTERNAL, "partial sums too large"); }
+      if (pos >= ((int64_t)1 << 31)) { return fail(FSI_ERR_INTERNAL, "partial sums too large"); }
       fpidx[f][k] = (int32_t)pos;
     }
   }
@@ -423,7 +461,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     while (lo < dh[i]) {
       const int G = std::min(sc.mob_group > 0 ? sc.mob_group : 6, dh[i] - lo);
       const int cb = std::min(lo, kMaxTileBits - G);
-      if (p >= kMaxMobPasses) { free_batch(P); return fail(FSI_ERR_INTERNAL, "too many passes"); }
+      if (p >= kMaxMobPasses) { return fail(FSI_ERR_INTERNAL, "too many passes"); }
       const int64_t nblk = (int64_t)1 << (dh[i] - G - cb);
       for (int64_t bk = 0; bk < nblk; ++bk) mob[p].push_back(MobItem{i, lo, G, cb, bk});
       lo += G;
@@ -477,7 +515,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   const size_t o_ooff = stage(buf, P->ooff.data(), P->ooff.size());
 
   hipError_t e = hipMalloc(&P->arena, buf.size());
-  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(tables) failed"); }
+  if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(tables) failed"); }
   auto* A = static_cast<unsigned char*>(P->arena);
   for (size_t c = 0; c < P->classes.size(); ++c) {
     const ClassHost& C = P->classes[c];
@@ -512,7 +550,6 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.gnkk = reinterpret_cast<const int32_t*>(A + fo[f].gnkk);
   }
   if (fast_lds_max > 160 * 1024) {
-    free_batch(P);
     return fail(FSI_ERR_INTERNAL, "register-phase kernel does not fit in LDS");
   }
   std::memcpy(buf.data() + o_fcls, fdev.data(), fdev.size() * sizeof(FastClassDev));
@@ -521,24 +558,25 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   // instance descriptors carry the fast fields filled above
   std::memcpy(buf.data() + o_inst, insts.data(), insts.size() * sizeof(InstDev));
   e = hipMemcpy(P->arena, buf.data(), buf.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, "hipMemcpy(tables) failed"); }
+  if (e != hipSuccess) { return fail(FSI_ERR_HIP, "hipMemcpy(tables) failed"); }
 
   e = hipMalloc(reinterpret_cast<void**>(&P->Y), std::max<int64_t>(ytot, 1) * sizeof(double));
-  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(Y) failed"); }
+  if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(Y) failed"); }
   if (algo == ALGO_TWO_PASS && !P->in_place) {
     const size_t wbytes = (size_t)wtot *
                           std::max(mob_elem_bytes(prec), (size_t)8);
     e = hipMalloc(&P->work, wbytes);
-    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(work) failed"); }
+    if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(work) failed"); }
   }
 
   if (ptot > 0) {
-    e = hipMalloc(reinterpret_cast<void**>(&P->partial), ptot * sizeof(double));
-    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(partial) failed"); }
+    e = test_fail_alloc("device") ? hipErrorOutOfMemory
+                                  : hipMalloc(reinterpret_cast<void**>(&P->partial), ptot * sizeof(double));
+    if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(partial) failed"); }
   }
   if (wptot > 0) {
     e = hipMalloc(reinterpret_cast<void**>(&P->wide_partial), wptot * sizeof(double));
-    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(wide partial) failed"); }
+    if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(wide partial) failed"); }
   }
 
   // ---- schedule ----
@@ -552,7 +590,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
                                                            ((size_t)1 << C.b) * mob_elem_bytes(prec)));
   }
   e = configure_kernels(prec, algo, tile_lds, mob_lds);
-  if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, std::string("configure_kernels: ") + hipGetErrorString(e)); }
+  if (e != hipSuccess) { return fail(FSI_ERR_HIP, std::string("configure_kernels: ") + hipGetErrorString(e)); }
   if (tile_lds == 0) tile_lds = 1024;
   const int per_cu = std::max(1, std::min<int>(4, (int)((160 * 1024) / std::max<size_t>(tile_lds, 1))));
   LaunchArgs& a = P->args;
@@ -594,7 +632,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.fast.n_items = (int)fitems.size();
   if (!fitems.empty()) {
     e = configure_fast(prec, fast_lds);
-    if (e != hipSuccess) { free_batch(P); return fail(FSI_ERR_HIP, std::string("configure_fast: ") + hipGetErrorString(e)); }
+    if (e != hipSuccess) { return fail(FSI_ERR_HIP, std::string("configure_fast: ") + hipGetErrorString(e)); }
     a.fast.prec = prec;
     a.fast.classes = reinterpret_cast<const FastClassDev*>(A + o_fcls);
     a.fast.insts = a.insts;
@@ -621,6 +659,15 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   P->sched.tile_shift = sc.tb_shift;
   P->sched.mob_group = algo == ALGO_TWO_PASS ? (sc.mob_group > 0 ? sc.mob_group : 6) : 0;
   P->sched.tuned_ms = 0.f;
+  P->partial_bytes = (size_t)ptot * sizeof(double);
+  P->y_bytes = (size_t)std::max<int64_t>(ytot, 1) * sizeof(double);
+  P->wide_bytes = (size_t)wptot * sizeof(double);
+  P->work_bytes = (algo == ALGO_TWO_PASS && !P->in_place)
+                      ? (size_t)wtot * std::max(mob_elem_bytes(prec), (size_t)8)
+                      : 0;
+  e = hipEventCreateWithFlags(&P->done, hipEventDisableTiming);
+  if (e != hipSuccess) { P->done = nullptr; return fail(FSI_ERR_HIP, "hipEventCreate failed"); }
+  guard.p = nullptr;
   *out = P;
   return FSI_OK;
 }
@@ -767,6 +814,26 @@ fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts*
 
 }  // namespace
 
+namespace {
+
+// Marks the plan's work on `stream` as issued: destroying the plan waits
+// for this event. Not recorded while the stream is being captured (the
+// caller's graph then owns the ordering).
+void mark_done(fsi_batch_plan_s* P, hipStream_t stream) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+    (void)hipEventRecord(P->done, stream);
+}
+
+fsi_status check_ptr(const void* p, const char* what) {
+  if (!p) return fail(FSI_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  if (reinterpret_cast<uintptr_t>(p) & 15)
+    return fail(FSI_ERR_INVALID_ARG, std::string(what) + " is not 16-byte aligned");
+  return FSI_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 fsi_status fsi_default_opts(fsi_plan_opts* opts) {
@@ -783,6 +850,7 @@ int64_t fsi_num_outputs(int d, int l) { return num_outputs(d, l); }
 fsi_status fsi_plan(int d, int l, fsi_plan_t* out) { return fsi_plan_ex(d, l, nullptr, out); }
 
 fsi_status fsi_plan_ex(int d, int l, const fsi_plan_opts* opts, fsi_plan_t* out) {
+  FSI_ABI_TRY
   if (!out) return fail(FSI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!(1 <= d && d <= kMaxD && 1 <= l && l <= d))
@@ -795,13 +863,16 @@ fsi_status fsi_plan_ex(int d, int l, const fsi_plan_opts* opts, fsi_plan_t* out)
   p->bp = bp; p->d = d; p->l = l;
   *out = p;
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_plan_destroy(fsi_plan_t plan) {
+  FSI_ABI_TRY
   if (!plan) return FSI_OK;
   free_batch(plan->bp);
   delete plan;
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_output_masks(fsi_plan_t plan, uint32_t* host_masks) {
@@ -814,31 +885,29 @@ fsi_status fsi_output_masks(fsi_plan_t plan, uint32_t* host_masks) {
 fsi_status fsi_plan_info(fsi_plan_t plan, int* tile_bits, int* block_threads, int* algo,
                          int* precision) {
   if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  const bool fast = plan->bp->sched.fast_instances > 0;
   if (tile_bits) *tile_bits = plan->bp->classes[0].b;
-  if (block_threads) *block_threads = kTileThreads;
+  if (block_threads) *block_threads = fast ? kFastThreads : kTileThreads;
   if (algo) *algo = plan->bp->algo;
   if (precision) *precision = plan->bp->prec;
   return FSI_OK;
 }
 
-static fsi_status check_ptr(const void* p, const char* what) {
-  if (!p) return fail(FSI_ERR_INVALID_ARG, std::string(what) + " is NULL");
-  if (reinterpret_cast<uintptr_t>(p) & 15)
-    return fail(FSI_ERR_INVALID_ARG, std::string(what) + " is not 16-byte aligned");
-  return FSI_OK;
-}
-
 fsi_status fsi_apply(fsi_plan_t plan, const void* v_dev, void* out_dev, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
   fsi_status st;
   if ((st = check_ptr(v_dev, "v_dev")) != FSI_OK) return st;
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
   LaunchArgs a = apply_args(plan->bp, v_dev, out_dev);
   HIP_TRY(launch_apply(a, stream));
+  mark_done(plan->bp, stream);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_mobius(fsi_plan_t plan, void* a_dev, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
   fsi_status st;
   if ((st = check_ptr(a_dev, "a_dev")) != FSI_OK) return st;
@@ -846,11 +915,14 @@ fsi_status fsi_mobius(fsi_plan_t plan, void* a_dev, hipStream_t stream) {
   a.work = a_dev;
   a.prec = plan->bp->dtype == FSI_DTYPE_F64 ? PREC_F64 : PREC_F32;
   HIP_TRY(launch_mobius(a, stream));
+  mark_done(plan->bp, stream);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_plan_batched(int n, const int* d_host, const int* l_host,
                             const fsi_plan_opts* opts, fsi_batch_plan_t* out) {
+  FSI_ABI_TRY
   if (!out) return fail(FSI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   fsi_batch_plan_s* bp = nullptr;
@@ -858,11 +930,14 @@ fsi_status fsi_plan_batched(int n, const int* d_host, const int* l_host,
   if (st != FSI_OK) return st;
   *out = bp;
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_batch_plan_destroy(fsi_batch_plan_t plan) {
+  FSI_ABI_TRY
   free_batch(plan);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_batch_offsets(fsi_batch_plan_t plan, int64_t* value_offset, int64_t* out_offset) {
@@ -874,24 +949,26 @@ fsi_status fsi_batch_offsets(fsi_batch_plan_t plan, int64_t* value_offset, int64
 
 fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan, const void* values_dev,
                                      void* out_dev, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
   fsi_status st;
   if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
   LaunchArgs a = apply_args(plan, values_dev, out_dev);
   HIP_TRY(launch_apply(a, stream));
+  mark_done(plan, stream);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_apply_batched(fsi_batch_plan_t plan, const void* values_dev, void* out_dev,
                              hipStream_t stream) {
+  FSI_ABI_TRY
   if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
   fsi_status st;
   if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
   if (!plan->exec || plan->g_in != values_dev || plan->g_out != out_dev) {
-    if (plan->exec) { HIP_TRY(hipGraphExecDestroy(plan->exec)); plan->exec = nullptr; }
-    if (plan->graph) { HIP_TRY(hipGraphDestroy(plan->graph)); plan->graph = nullptr; }
     if (!plan->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
     LaunchArgs a = apply_args(plan, values_dev, out_dev);
     HIP_TRY(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -903,13 +980,31 @@ fsi_status fsi_apply_batched(fsi_batch_plan_t plan, const void* values_dev, void
       return fail(FSI_ERR_HIP, std::string("launch during capture: ") + hipGetErrorString(le));
     }
     if (ce != hipSuccess) return fail(FSI_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+    // the launch sequence does not depend on the pointers: a new pointer
+    // pair updates the kernel arguments of the instantiated graph in place
+    // (re-instantiated only if the update is refused)
+    bool updated = false;
+    if (plan->exec) {
+      hipGraphExecUpdateResult ur = hipGraphExecUpdateError;
+      hipGraphNode_t bad = nullptr;
+      updated = hipGraphExecUpdate(plan->exec, g, &bad, &ur) == hipSuccess &&
+                ur == hipGraphExecUpdateSuccess;
+      if (!updated) {
+        (void)hipGetLastError();
+        HIP_TRY(hipGraphExecDestroy(plan->exec));
+        plan->exec = nullptr;
+      }
+    }
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
     plan->graph = g;
-    HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+    if (!updated) HIP_TRY(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
     plan->g_in = values_dev;
     plan->g_out = out_dev;
   }
   HIP_TRY(hipGraphLaunch(plan->exec, stream));
+  mark_done(plan, stream);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 int fsi_batch_num_stages(fsi_batch_plan_t plan) {
@@ -919,6 +1014,7 @@ int fsi_batch_num_stages(fsi_batch_plan_t plan) {
 
 fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev, void* out_dev,
                                    int stage, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
   fsi_status st;
   if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
@@ -927,7 +1023,9 @@ fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev
     return fail(FSI_ERR_INVALID_ARG, "stage out of range");
   LaunchArgs a = apply_args(plan, values_dev, out_dev);
   HIP_TRY(launch_stage(a, stage, stream));
+  mark_done(plan, stream);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_batch_schedule(fsi_batch_plan_t plan, fsi_schedule* out) {

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/fsi_forest.h"
+#include "fsi_abi.h"
 #include "fsi_internal.h"
 
 namespace fsi {
@@ -380,6 +381,7 @@ fsi_status fsi_forest_create(int d, int n_trees, const int32_t* roots, int n_nod
                              const int32_t* feature, const double* threshold,
                              const int32_t* left, const int32_t* right, const double* value,
                              int max_bg, fsi_forest_t* out) {
+  FSI_ABI_TRY
   if (!out) return ffail(FSI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (!(1 <= d && d <= kMaxD)) return ffail(FSI_ERR_INVALID_ARG, "need 1 <= d <= 30");
@@ -409,6 +411,11 @@ fsi_status fsi_forest_create(int d, int n_trees, const int32_t* roots, int n_nod
 
   auto* F = new (std::nothrow) fsi_forest_s();
   if (!F) return ffail(FSI_ERR_OUT_OF_MEMORY, "host allocation failed");
+  // frees the partly built forest on every failure below, thrown or returned
+  struct Guard {
+    fsi_forest_s* f;
+    ~Guard() { free_forest(f); }
+  } guard{F};
   F->d = d; F->n_trees = n_trees; F->n_nodes = n_nodes; F->max_bg = max_bg;
   F->max_depth = depth; F->device = dev;
   // leaves keep feature -1 on the device whatever negative value they had
@@ -441,21 +448,25 @@ fsi_status fsi_forest_create(int d, int n_trees, const int32_t* roots, int n_nod
     }
   }
   if (e != hipSuccess) {
-    free_forest(F);
     return ffail(e == hipErrorOutOfMemory ? FSI_ERR_OUT_OF_MEMORY : FSI_ERR_HIP,
                  std::string("forest upload: ") + hipGetErrorString(e));
   }
+  guard.f = nullptr;
   *out = F;
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_forest_destroy(fsi_forest_t forest) {
+  FSI_ABI_TRY
   free_forest(forest);
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_forest_values(fsi_forest_t F, const double* x_dev, int n_bg, const double* bg_dev,
                              int dtype, void* v_dev, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!F) return ffail(FSI_ERR_INVALID_ARG, "forest is NULL");
   if (!x_dev || !bg_dev || !v_dev) return ffail(FSI_ERR_INVALID_ARG, "null device pointer");
   if (n_bg < 1 || n_bg > F->max_bg)
@@ -483,10 +494,12 @@ fsi_status fsi_forest_values(fsi_forest_t F, const double* x_dev, int n_bg, cons
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(FSI_ERR_HIP, std::string("forest launch: ") + hipGetErrorString(e));
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_forest_mobius(fsi_forest_t F, const double* x_dev, int n_bg, const double* bg_dev,
                              double* a_dev, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!F) return ffail(FSI_ERR_INVALID_ARG, "forest is NULL");
   if (!x_dev || !bg_dev || !a_dev) return ffail(FSI_ERR_INVALID_ARG, "null device pointer");
   if (n_bg < 1 || n_bg > F->max_bg)
@@ -507,11 +520,13 @@ fsi_status fsi_forest_mobius(fsi_forest_t F, const double* x_dev, int n_bg, cons
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(FSI_ERR_HIP, std::string("forest launch: ") + hipGetErrorString(e));
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 fsi_status fsi_forest_values_mobius(fsi_forest_t F, const double* x_dev, int n_bg,
                                     const double* bg_dev, double* work_dev, int dtype,
                                     void* v_dev, hipStream_t stream) {
+  FSI_ABI_TRY
   if (!F) return ffail(FSI_ERR_INVALID_ARG, "forest is NULL");
   if (!v_dev) return ffail(FSI_ERR_INVALID_ARG, "null device pointer");
   if (dtype != FSI_DTYPE_F64 && dtype != FSI_DTYPE_F32)
@@ -544,6 +559,7 @@ fsi_status fsi_forest_values_mobius(fsi_forest_t F, const double* x_dev, int n_b
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return ffail(FSI_ERR_HIP, std::string("forest launch: ") + hipGetErrorString(e));
   return FSI_OK;
+  FSI_ABI_CATCH
 }
 
 }  // extern "C"

@@ -98,7 +98,7 @@ tile_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ in
 
     if constexpr (kMobius) {
       // in-tile Moebius butterfly over the b low bits (Kronecker factors
-      // [[1, 0], [-1, 1]], Sec. 3.2), staged in LDS in the Moebius type
+      // [[1, 0], [-1, 1]], Sec. 4.2), staged in LDS in the Moebius type
       MobT* m = reinterpret_cast<MobT*>(smem);
       const SrcT* v = src + I.voff + ((int64_t)w.tile << b);
       for (int i = tid; i < nt; i += NT) m[i] = Num<MobT>::from_in(v[i]);

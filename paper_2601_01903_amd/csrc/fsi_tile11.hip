@@ -4,7 +4,7 @@
 // A workgroup of 256 threads owns a work item: a run of tiles of one
 // instance (raw v, high index U_H) and one group of its outputs. Per tile it
 // computes
-//   - the in-tile Moebius butterfly (Sec. 3.2) over the 11 low bits: bits
+//   - the in-tile Moebius butterfly (Sec. 4.2) over the 11 low bits: bits
 //     8-10 in registers straight from the coalesced loads, bits 4-7 and 0-3
 //     through two LDS transposes;
 //   - the left-to-right counter sweep (Sec. 4.3 - 4.4) in three phases of 4,

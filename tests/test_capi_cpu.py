@@ -127,3 +127,41 @@ def test_forest_validation_before_device_use():
     lib = fsi.load()
     assert lib.fsi_forest_destroy(None) == 0
     assert lib.fsi_forest_values(None, None, 1, None, 0, None, None) == 1
+
+
+def test_host_allocation_failure_returns_status(monkeypatch):
+    """A std::bad_alloc while a plan is built comes back as
+    FSI_ERR_OUT_OF_MEMORY with a message, through every plan entry point; no
+    exception crosses the ABI (the process would abort)."""
+    lib = fsi.load()
+    monkeypatch.setenv("FSI_TEST_FAIL_ALLOC", "host")
+    h = ctypes.c_void_p()
+    assert lib.fsi_plan(12, 3, ctypes.byref(h)) == 3
+    assert h.value is None
+    assert b"host allocation failed" in lib.fsi_last_error()
+    darr = (ctypes.c_int * 3)(20, 12, 9)
+    larr = (ctypes.c_int * 3)(4, 3, 2)
+    assert lib.fsi_plan_batched(3, darr, larr, None, ctypes.byref(h)) == 3
+    assert h.value is None
+    o = fsi.Opts()
+    lib.fsi_default_opts(ctypes.byref(o))
+    o.dtype, o.autotune = 1, 1
+    assert lib.fsi_plan_ex(20, 4, ctypes.byref(o), ctypes.byref(h)) == 3
+    assert h.value is None
+    # argument errors still win over the hook
+    assert lib.fsi_plan(4, 0, ctypes.byref(h)) == 1
+    monkeypatch.delenv("FSI_TEST_FAIL_ALLOC")
+    # without the hook this host has no gfx950 device
+    if not fsi.torch.cuda.is_available():
+        assert lib.fsi_plan(12, 3, ctypes.byref(h)) == 2
+
+
+def test_block_threads_is_reserved():
+    lib = fsi.load()
+    o = fsi.Opts()
+    lib.fsi_default_opts(ctypes.byref(o))
+    h = ctypes.c_void_p()
+    for bt in (256, 512, -1):
+        o.block_threads = bt
+        assert lib.fsi_plan_ex(12, 3, ctypes.byref(o), ctypes.byref(h)) == 1
+        assert b"block_threads" in lib.fsi_last_error()
