@@ -266,6 +266,22 @@ fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan,
                                      const void* values_dev, void* out_dev,
                                      hipStream_t stream);
 
+/* For callers that cannot allocate device memory at apply time (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * fsi_apply_batched_nograph with the plan's device workspaces (partial sums,
+ * per-tile results, two-pass Moebius workspace) taken from a static device
+ * scratch array of 64 MiB per GPU instead of the plan's own buffers. It
+ * calls no hipMalloc, hipFree or other allocating routine. Plans whose
+ * workspaces need more than 64 MiB (e.g. d above about 24 at l = 4 on the
+ * generic kernel) get FSI_ERR_INVALID_ARG; so does a call whose current HIP
+ * device is not the plan's. Every such call on one GPU shares that GPU's
+ * array: calls that overlap in time on one GPU (other streams, other
+ * threads) race, and the array keeps the last call's contents (no kernel
+ * reads a word the same call has not written). Same outputs as
+ * fsi_apply_batched_nograph. */
+fsi_status fsi_apply_batched_noalloc(fsi_batch_plan_t plan,
+                                     const void* values_dev, void* out_dev,
+                                     hipStream_t stream);
 
 /* The kernel launches of one batched apply, for per-kernel timing. The
  * fused algorithm launches, in this order and each only if the plan has

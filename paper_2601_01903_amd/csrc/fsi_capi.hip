@@ -100,7 +100,8 @@ struct fsi_batch_plan_s {
   LaunchArgs args{};
   // bytes of each device workspace an apply writes and reads back (partial
   // sums, per-tile results, wide-gather partials, two-pass Moebius
-  // workspace)
+  // workspace): the no-allocation entry point carves them from its static
+  // scratch array instead
   size_t partial_bytes = 0, y_bytes = 0, wide_bytes = 0, work_bytes = 0;
   // recorded after every apply on the caller's stream (outside stream
   // capture): destroying the plan waits for it, not for the whole device
@@ -814,7 +815,47 @@ fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts*
 
 }  // namespace
 
+// ------------------------------------------------ no-allocation scratch
+// Device scratch of fsi_apply_batched_noalloc: a fixed-size array in the
+// library's code object, one copy per GPU the library runs on (held until
+// the process ends). In host code the array's name is only a host-side
+// stand-in: its device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and only that address is passed to
+// kernels. Every no-allocation apply on a GPU carves its workspaces from the
+// same array, so such calls that overlap on one GPU race; the array keeps
+// the last call's contents (no kernel of an apply reads a workspace word
+// before the same apply has written it, so nothing needs clearing).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kScratchMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchMaxDevices] = {};
+
+// Device address of this device's scratch array (current device = dev).
+fsi_status scratch_address(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kScratchMaxDevices)
+    return fail(FSI_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FSI_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return FSI_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t scratch_need(const fsi_batch_plan_s* P) {
+  return align256(P->partial_bytes) + align256(P->y_bytes) + align256(P->wide_bytes) +
+         align256(P->work_bytes);
+}
 
 // Marks the plan's work on `stream` as issued: destroying the plan waits
 // for this event. Not recorded while the stream is being captured (the
@@ -955,6 +996,41 @@ fsi_status fsi_apply_batched_nograph(fsi_batch_plan_t plan, const void* values_d
   if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
   if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
   LaunchArgs a = apply_args(plan, values_dev, out_dev);
+  HIP_TRY(launch_apply(a, stream));
+  mark_done(plan, stream);
+  return FSI_OK;
+  FSI_ABI_CATCH
+}
+
+fsi_status fsi_apply_batched_noalloc(fsi_batch_plan_t plan, const void* values_dev,
+                                     void* out_dev, hipStream_t stream) {
+  FSI_ABI_TRY
+  if (!plan) return fail(FSI_ERR_INVALID_ARG, "null plan");
+  fsi_status st;
+  if ((st = check_ptr(values_dev, "values_dev")) != FSI_OK) return st;
+  if ((st = check_ptr(out_dev, "out_dev")) != FSI_OK) return st;
+  const size_t need = scratch_need(plan);
+  if (need > kScratchBytes)
+    return fail(FSI_ERR_INVALID_ARG,
+                "the plan's workspaces need " + std::to_string(need) +
+                    " bytes; the no-allocation scratch holds " + std::to_string(kScratchBytes));
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != plan->device)
+    return fail(FSI_ERR_INVALID_ARG, "the current HIP device is not the plan's device");
+  unsigned char* base = nullptr;
+  if ((st = scratch_address(dev, &base)) != FSI_OK) return st;
+  LaunchArgs a = apply_args(plan, values_dev, out_dev);
+  size_t off = 0;
+  double* part = plan->partial_bytes ? reinterpret_cast<double*>(base + off) : nullptr;
+  a.partial = part;
+  a.fast.partial = part;
+  off += align256(plan->partial_bytes);
+  a.Y = reinterpret_cast<double*>(base + off);
+  off += align256(plan->y_bytes);
+  a.wide_partial = plan->wide_bytes ? reinterpret_cast<double*>(base + off) : nullptr;
+  off += align256(plan->wide_bytes);
+  if (plan->work_bytes) a.work = base + off;
   HIP_TRY(launch_apply(a, stream));
   mark_done(plan, stream);
   return FSI_OK;

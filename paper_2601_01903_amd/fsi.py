@@ -31,6 +31,7 @@ EXPORTS = ["fsi_default_opts", "fsi_num_outputs", "fsi_plan", "fsi_plan_ex",
            "fsi_plan_destroy", "fsi_output_masks", "fsi_plan_info", "fsi_apply",
            "fsi_mobius", "fsi_plan_batched", "fsi_batch_plan_destroy",
            "fsi_batch_offsets", "fsi_apply_batched", "fsi_apply_batched_nograph",
+           "fsi_apply_batched_noalloc",
            "fsi_batch_num_stages", "fsi_apply_batched_stage", "fsi_plan_schedule",
            "fsi_batch_schedule", "fsi_last_error",
            "fsi_forest_create", "fsi_forest_destroy", "fsi_forest_values",
@@ -91,6 +92,7 @@ def load() -> ctypes.CDLL:
     lib.fsi_batch_offsets.argtypes = [vp, P(i64), P(i64)]
     lib.fsi_apply_batched.argtypes = [vp, vp, vp, vp]
     lib.fsi_apply_batched_nograph.argtypes = [vp, vp, vp, vp]
+    lib.fsi_apply_batched_noalloc.argtypes = [vp, vp, vp, vp]
     lib.fsi_batch_num_stages.argtypes = [vp]
     lib.fsi_apply_batched_stage.argtypes = [vp, vp, vp, i32, vp]
     lib.fsi_plan_schedule.argtypes = [vp, P(Schedule)]
@@ -270,6 +272,18 @@ class BatchPlan:
         fn = load().fsi_apply_batched if graph else load().fsi_apply_batched_nograph
         _check(fn(self._h, ctypes.c_void_p(values.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                   _stream_handle(stream)), "fsi_apply_batched")
+        return out
+
+    def apply_noalloc(self, values: torch.Tensor, out: torch.Tensor, stream=None) -> torch.Tensor:
+        """fsi_apply_batched_noalloc: the workspaces come from the library's
+        static per-GPU scratch array; the caller passes both buffers."""
+        dt = _TORCH_DTYPE[self.dtype]
+        _check_tensor(values, self.value_offset[-1], dt, "values")
+        _check_tensor(out, self.out_offset[-1], dt, "out")
+        _check(load().fsi_apply_batched_noalloc(self._h, ctypes.c_void_p(values.data_ptr()),
+                                                ctypes.c_void_p(out.data_ptr()),
+                                                _stream_handle(stream)),
+               "fsi_apply_batched_noalloc")
         return out
 
     def schedule(self) -> dict:
