@@ -304,17 +304,28 @@ def mpo_cores(d, l, precontract=False):
     return cores
 
 
-def mpo_apply(cores, x, d):
-    """Contract the MPO with a vector x of length 2^d, one site at a time.
-    Site k is bit (d - k) of the mask (the first site is the most significant
-    bit, as in a row-major reshape). Returns the full output vector u."""
-    X = np.asarray(x, dtype=np.float64).reshape(1, 1, 1 << d)
-    for k, G in enumerate(cores, start=1):
-        P, D, R = X.shape
-        Xr = X.reshape(P, D, 2, R // 2)                 # split off tau_k
-        Y = np.einsum("pdtr,dstb->psbr", Xr, G)          # sum over alpha, tau
-        X = Y.reshape(P * 2, G.shape[3], R // 2)
-    return X.reshape(1 << d)
+def mpo_apply(cores, x, d, l):
+    """Outputs u[S], |S| <= l, of the operator the MPO represents, applied to
+    x (length 2^d). By definition of an MPO, its matrix entry for output S and
+    input T is the product of the core slices along the sites,
+        M[S, T] = G1[., s_1(S), t_1(T), .] G2[., s_2(S), t_2(T), .] ... Gd[...],
+    a 1 x 1 matrix (the first and last bond dimensions are 1); site k reads
+    bit d - k of the masks (the first site is the most significant bit). So
+    u[S] = sum_T M[S, T] x[T], evaluated here pair by pair (all T at once for
+    one S, the slice product carried as a row vector per T)."""
+    x = np.asarray(x, dtype=np.float64)
+    T = np.arange(1 << d)
+    out = {}
+    for S in _subsets_upto(d, l):
+        row = np.ones((T.size, 1))
+        for k, G in enumerate(cores, start=1):
+            bit = d - k
+            sig = (S >> bit) & 1
+            tau = (T >> bit) & 1                       # per input T
+            slices = G[:, sig, :, :].transpose(1, 0, 2)[tau]   # (n_T, D_prev, D_next)
+            row = np.einsum("nd,nde->ne", row, slices)
+        out[S] = float(row[:, 0] @ x)
+    return out
 
 
 def fsi_via_mpo(v, d, l, precontract=False):
@@ -324,12 +335,11 @@ def fsi_via_mpo(v, d, l, precontract=False):
     v = np.asarray(v, dtype=np.float64)
     from_oracle_free_mobius = _mobius_by_definition(v, d)
     if precontract:
-        corr = mpo_apply(mpo_cores(d, l, precontract=True), v, d)
+        corr = mpo_apply(mpo_cores(d, l, precontract=True), v, d, l)
     else:
-        corr = mpo_apply(mpo_cores(d, l), from_oracle_free_mobius, d)
-    full = from_oracle_free_mobius + corr
+        corr = mpo_apply(mpo_cores(d, l), from_oracle_free_mobius, d, l)
     S_list = sorted(_subsets_upto(d, l), key=lambda m: (_pc(m), m))
-    return np.array([full[S] for S in S_list])
+    return np.array([from_oracle_free_mobius[S] + corr[S] for S in S_list])
 
 
 def _mobius_by_definition(v, d):

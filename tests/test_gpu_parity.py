@@ -88,22 +88,58 @@ def test_d20_fp64(l, algo):
     assert err < INT_TOL[algo]
 
 
-@pytest.mark.parametrize("prec", ["f32", "f32_compensated", "f32_fp64mob", "f32_fp64reg"])
+_D20_REFS = {}
+
+
+def _d20_refs(l):
+    """Oracle references of the d = 20 inputs on their FP32 values: the tree
+    game (FP64 oracle) and the +/-1 vector (exact-integer oracle)."""
+    if l not in _D20_REFS:
+        g, v = games.d20_tree(0)
+        v32 = v.astype(np.float32)
+        vp = games.d20_pm1(0).astype(np.float32)
+        _D20_REFS[l] = (v32, oracle.fsi_c(v32.astype(np.float64), 20, l, nthreads=16),
+                        vp, oracle.fsi_exact_int(vp.astype(np.float64), 20, l, nthreads=16))
+    return _D20_REFS[l]
+
+
+@pytest.mark.parametrize("l", [2, 4])
+@pytest.mark.parametrize("prec", ["f32", "f32_compensated", "f32_fp64mob", "auto", "f32_fp64reg"])
 @pytest.mark.parametrize("algo", ["fused", "two_pass"])
-def test_d20_fp32_modes(prec, algo):
-    say(f"[case] d=20 l=4 FP32 storage prec={prec} algo={algo}")
-    g, v = games.d20_tree(0)
-    v32 = v.astype(np.float32)
-    ref = oracle.fsi_c(v32.astype(np.float64), 20, 4, nthreads=8)
-    got, _ = gpu_apply(v32, 20, 4, dtype="f32", precision=prec, algo=algo)
+def test_d20_fp32_modes(prec, algo, l):
+    """d = 20, l in {2, 4}, FP32 storage, every precision form: the tree game
+    within 1e-6 of the oracle on the same FP32 values. On the +/-1 vector the
+    fused algorithm is exact through the FP32 tile (in-tile Moebius values
+    are integers below 2^11, in-tile sums below 2^22, the high-site Moebius
+    is folded into FP64 weights), so its only error is the final rounding of
+    each output to FP32 storage: every output within one FP32 ulp of the
+    exact-integer oracle (relative 2^-23), normwise at most 2^-24. The
+    two-pass algorithm with the FP64 sweep is held to the same normwise
+    bound (its FP64 products of full-range Moebius values with the weights
+    leave an absolute error near 1e-11 of the largest output, above one ulp
+    of the smallest outputs). The two-pass FP32 sweep adds full-range
+    Moebius values (up to 2^20) in FP32: held to the FP32 tolerance."""
+    say(f"[case] d=20 l={l} FP32 storage prec={prec} algo={algo}")
+    v32, ref, vp, refp = _d20_refs(l)
+    got, _ = gpu_apply(v32, 20, l, dtype="f32", precision=prec, algo=algo)
     err = normwise(got, ref)
     say(f"  tree normwise err {err:.3e}")
     assert err < 1e-6
-    vp = games.d20_pm1(0).astype(np.float32)
-    refp = oracle.fsi_exact_int(vp.astype(np.float64), 20, 4, nthreads=8)
-    gotp, _ = gpu_apply(vp, 20, 4, dtype="f32", precision=prec, algo=algo)
-    say(f"  +/-1 normwise err {normwise(gotp, refp):.3e} (reported, not gated)")
+    gotp, _ = gpu_apply(vp, 20, l, dtype="f32", precision=prec, algo=algo)
+    errp = normwise(gotp, refp)
     assert np.all(np.isfinite(gotp))
+    if algo == "fused":
+        ulp = np.max(np.abs(gotp - refp) / np.maximum(np.abs(refp), 1e-300))
+        say(f"  +/-1 normwise err {errp:.3e}, max elementwise {ulp:.3e} "
+            f"(gated: normwise <= 2^-24, elementwise <= 2^-23, the FP32 output rounding)")
+        assert errp <= 2.0 ** -24 * (1 + 1e-6)
+        assert np.all(np.abs(gotp - refp) <= 2.0 ** -23 * np.abs(refp) + 1e-13 * np.max(np.abs(refp)))
+    elif prec == "f32_fp64reg":
+        say(f"  +/-1 normwise err {errp:.3e} (gated: normwise <= 2^-24 + 1e-11)")
+        assert errp <= 2.0 ** -24 + 1e-11
+    else:
+        say(f"  +/-1 normwise err {errp:.3e} (two-pass FP32 sweep: gated at 1e-6)")
+        assert errp < 1e-6
 
 
 @pytest.mark.parametrize("kernel", ["generic", "register"])
@@ -169,27 +205,41 @@ def _ragged_batch():
     return ds, ls, [v for _, v in built]
 
 
-@pytest.mark.parametrize("prec", ["f32_compensated", "f32"])
-def test_ragged_batch_512_fp32(prec):
+_RAGGED_REFS = {}
+
+
+def _ragged_refs(ds, ls, v32):
+    """Oracle of every ragged instance on its FP32 values (computed once)."""
+    if "r" not in _RAGGED_REFS:
+        _RAGGED_REFS["r"] = [oracle.fsi_c(v.astype(np.float64), d, l, nthreads=16)
+                             for v, d, l in zip(v32, ds, ls)]
+    return _RAGGED_REFS["r"]
+
+
+@pytest.mark.parametrize("prec,autotune", [("auto", True), ("f32_fp64mob", False),
+                                           ("f32_compensated", False), ("f32", False)])
+def test_ragged_batch_512_fp32(prec, autotune):
     """The 512-instance ragged batch (d ~ U{8..20}, l ~ U{1..4}, tree games),
     FP32 storage, one graph replay, every instance against the oracle on the
-    same FP32 values: <= 1e-6 normwise."""
+    same FP32 values: <= 1e-6 normwise; the default form both autotuned (the
+    launch the benchmark times) and with the default schedule."""
     fsi = fsi_mod()
     ds, ls, vals = _ragged_batch()
-    say(f"[case] ragged batch n={len(ds)} {prec}, {sum(1 << d for d in ds)} values")
+    say(f"[case] ragged batch n={len(ds)} {prec} autotune={autotune}, "
+        f"{sum(1 << d for d in ds)} values")
     v32 = [v.astype(np.float32) for v in vals]
-    bp = fsi.BatchPlan(ds, ls, dtype="f32", precision=prec)
+    refs = _ragged_refs(ds, ls, v32)
+    bp = fsi.BatchPlan(ds, ls, dtype="f32", precision=prec, autotune=autotune)
     flat = torch.from_numpy(np.concatenate(v32)).to(DEV)
     out = bp.apply(flat, graph=True)
     torch.cuda.synchronize()
     o = out.double().cpu().numpy()
-    worst = 0.0
-    for i, (v, d, l) in enumerate(zip(v32, ds, ls)):
-        ref = oracle.fsi_c(v.astype(np.float64), d, l, nthreads=16)
-        err = normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], ref)
-        worst = max(worst, err)
+    errs = []
+    for i, (d, l) in enumerate(zip(ds, ls)):
+        err = normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], refs[i])
+        errs.append(err)
         assert err < 1e-6, (i, d, l, err)
-    say(f"  worst normwise err {worst:.3e}")
+    say(f"  normwise max {max(errs):.3e} median {float(np.median(errs)):.3e}")
     bp.close()
 
 

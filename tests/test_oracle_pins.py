@@ -381,3 +381,62 @@ def test_exact_int_oracle_matches_pin(d, l):
     ref = P.fsi_exact_int(v.astype(np.int64), d, l)
     assert np.array_equal(oracle.fsi_exact_int(v, d, l), ref)
     assert np.array_equal(oracle.fsi_exact_int(v, d, l, nthreads=4), ref)
+
+
+# ---------------------------------------------------------------------------
+# oracle/closed_forms.py: the sparse-Moebius closed forms used for the
+# 256-instance d = 20 check, pinned against the brute-force oracle on the
+# game's values and against the term-by-term derivation in pins_lib
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d,l,depth", [(8, 2, 4), (10, 3, 5), (12, 4, 6), (11, 1, 6)])
+def test_closed_form_tree_games(d, l, depth):
+    from oracle import closed_forms as CF
+    g = games.tree_game(d, 25, depth, games.rng_for(77, 10 * d + l))
+    v = games.tree_values(g)
+    masks, coefs = CF.tree_mobius_sparse(g)
+    dense = np.zeros(1 << d)
+    dense[masks] = coefs
+    # the path-product Moebius coefficients are the Moebius transform of v
+    assert np.max(np.abs(dense - oracle.mobius(v))) < 1e-12 * max(1.0, np.max(np.abs(v)))
+    # the closed form equals the brute-force oracle on v
+    E = CF.fsi_from_sparse_mobius(masks, coefs, d, l)
+    ref = oracle.fsi(v, d, l)
+    assert np.max(np.abs(E - ref)) <= 1e-13 * np.max(np.abs(ref))
+    # and the independent derivation of the same facts
+    E2 = P.fsi_sparse_mobius(list(P.tree_mobius_terms(g).items()), d, l)
+    assert np.max(np.abs(E - E2)) <= 1e-13 * np.max(np.abs(ref))
+    # efficiency: sum of E over |S| <= l equals v(full set)
+    assert abs(E.sum() - v[-1]) <= 1e-12 * max(1.0, abs(v[-1]))
+
+
+@pytest.mark.parametrize("d,l,kmax", [(8, 2, 4), (12, 3, 6), (14, 4, 6)])
+def test_closed_form_planted_games(d, l, kmax):
+    from oracle import closed_forms as CF
+    g = games.planted_game(d, 60, kmax, games.rng_for(78, 10 * d + l))
+    v = games.planted_values(g)
+    masks, coefs = CF.planted_mobius_sparse(g)
+    E = CF.fsi_from_sparse_mobius(masks, coefs, d, l)
+    ref = oracle.fsi(v, d, l)
+    assert np.max(np.abs(E - ref)) <= 1e-13 * np.max(np.abs(ref))
+    E2 = P.fsi_sparse_mobius(list(zip(g.masks, g.coefs)), d, l)
+    assert np.max(np.abs(E - E2)) <= 1e-13 * np.max(np.abs(ref))
+
+
+def test_closed_form_catches_a_wrong_weight(monkeypatch):
+    """A plausible slip in the closed form (a weight of the wrong order, a
+    dropped Moebius term) fails the brute-force comparison."""
+    from oracle import closed_forms as CF
+    d, l = 10, 3
+    g = games.tree_game(d, 25, 5, games.rng_for(79, 0))
+    v = games.tree_values(g)
+    masks, coefs = CF.tree_mobius_sparse(g)
+    ref = oracle.fsi(v, d, l)
+    real = CF._weight_f64
+    CF._weight_f64.cache_clear()
+    monkeypatch.setattr(CF, "_weight_f64", lambda s, t, ll: real(s, t, ll + 1) if t > ll + 1 else 0.0)
+    bad = CF.fsi_from_sparse_mobius(masks, coefs, d, l)
+    assert np.max(np.abs(bad - ref)) > 1e-6 * np.max(np.abs(ref))
+    monkeypatch.undo()
+    keep = CF._popcount64(masks) > l
+    bad2 = CF.fsi_from_sparse_mobius(masks[keep], coefs[keep], d, l)
+    assert np.max(np.abs(bad2 - ref)) > 1e-6 * np.max(np.abs(ref))
