@@ -74,6 +74,23 @@ def measured_traffic(workload_key: str):
         return None
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def elementwise(x, ref, floor_frac=1e-3):
+    """Secondary error: max |x_S - ref_S| / |ref_S| over |ref_S| >= floor_frac max |ref|."""
+    keep = np.abs(ref) >= floor_frac * np.max(np.abs(ref))
+    return float(np.max(np.abs(x[keep] - ref[keep]) / np.abs(ref[keep])))
+
+
 def normwise(x, ref):
     den = float(np.max(np.abs(ref)))
     return float(np.max(np.abs(x - ref)) / den) if den else float(np.max(np.abs(x)))
@@ -270,6 +287,12 @@ def main():
                     help="skip generating the tree games' value functions on the GPU")
     ap.add_argument("--no-indices", action="store_true",
                     help="skip the other interaction indices (SII, k-SII, STII, BII) on the workload")
+    ap.add_argument("--no-ragged", action="store_true",
+                    help="skip the 512-instance ragged batch")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the d = 20 single instances at l = 2 and 4")
+    ap.add_argument("--no-closed-form", dest="closed_form", action="store_false",
+                    help="skip checking every headline instance against its closed form")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the heuristic schedule instead of timing candidates at plan time")
     args = ap.parse_args()
@@ -437,6 +460,79 @@ def main():
             pl.close()
             del xl, ol
 
+    # ---- the 512-instance ragged batch (d ~ U{8..20}, l ~ U{1..4}, tree
+    # games, FP32 storage, the default precision form, autotuned): one graph
+    # replay per step, the per-kernel stage times beside it ----
+    ragged, ragged_ctx = None, None
+    if not args.no_ragged:
+        rds, rls = games.ragged_specs(512)
+        rbuilt = games.build_many(lambda i: games.ragged_instance(i, rds[i]), range(len(rds)),
+                                  threads=threads)
+        rv32 = np.concatenate([v for _, v in rbuilt]).astype(np.float32)
+        del rbuilt
+        rx = torch.from_numpy(rv32).to(dev)
+        rbp = BatchPlan(rds, rls, dtype="f32", precision=args.precision,
+                        autotune=not args.no_autotune)
+        rout = rbp.apply(rx, graph=True)
+        rns = rbp.num_stages()
+        for _ in range(args.warmup):
+            rbp.apply(rx, rout, graph=True)
+            for s_ in range(rns):
+                rbp.apply_stage(rx, rout, s_)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            rbp.apply(rx, rout, graph=True)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        rms = ev0.elapsed_time(ev1) / args.steps
+        revs = [[torch.cuda.Event(enable_timing=True) for _ in range(rns + 1)]
+                for _ in range(args.steps)]
+        for k in range(args.steps):
+            revs[k][0].record(stream)
+            for s_ in range(rns):
+                rbp.apply_stage(rx, rout, s_)
+                revs[k][s_ + 1].record(stream)
+        torch.cuda.synchronize()
+        rstage = [float(np.mean([revs[k][s_].elapsed_time(revs[k][s_ + 1])
+                                 for k in range(args.steps)])) for s_ in range(rns)]
+        rvals = rbp.value_offset[-1]
+        rbytes = rvals * 4 + rbp.out_offset[-1] * 4
+        ragged = {"n_instances": len(rds), "values": rvals, "outputs": rbp.out_offset[-1],
+                  "ms_per_step": rms, "values_per_s": rvals / (rms * 1e-3),
+                  "algorithmic_bytes": rbytes,
+                  "hbm_frac": rbytes / (rms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                  "stage_ms": rstage, "sum_stage_ms": float(sum(rstage)),
+                  "schedule": rbp.schedule(), "precision": args.precision,
+                  "what": "512 instances, d ~ U{8..20}, l ~ U{1..4}, each its own tree game "
+                          "(100 depth-5 trees), FP32 storage, graph replay"}
+        ragged_ctx = {"ds": rds, "ls": rls, "v32": rv32, "out": rout.double().cpu().numpy(),
+                      "ooff": list(rbp.out_offset), "voff": list(rbp.value_offset)}
+        rbp.close()
+        del rx, rout
+        log(f"ragged batch: {rms:.3f} ms/step, {ragged['values_per_s']:.3e} values/s, "
+            f"{ragged['hbm_frac']:.3f} of HBM peak; stages {['%.4f' % x for x in rstage]}")
+
+    # ---- d = 20 single instances at l = 2 and 4: the FP64 path and the FP32
+    # forms on a tree game (200 depth-6 trees) and an i.i.d. +/-1 vector ----
+    c3, c3_ctx = None, None
+    if not args.no_c3:
+        g3, v3 = games.d20_tree(0)
+        vp3 = games.d20_pm1(0)
+        c3_ctx = {"tree": v3, "pm1": vp3, "got": {}}
+        c3 = {}
+        for l3 in (2, 4):
+            for vname, vv in (("tree", v3), ("pm1", vp3)):
+                for form in ("f64", "f32_fp64mob", "f32_compensated", "f32"):
+                    dt = "f64" if form == "f64" else "f32"
+                    pl3 = Plan(20, l3, dtype=dt, precision="f64" if form == "f64" else form)
+                    xv = torch.from_numpy(vv.astype(np.float64 if dt == "f64" else np.float32)).to(dev)
+                    o3 = pl3.apply(xv)
+                    torch.cuda.synchronize()
+                    c3_ctx["got"][(l3, vname, form)] = o3.double().cpu().numpy()
+                    pl3.close()
+        log("d=20 single instances at l = 2, 4 computed")
+
     # ---- FP64 paths on the same instances ----
     fp64 = None
     errs = None
@@ -533,6 +629,63 @@ def main():
                                           "single-coalition walk"}
             log(f"value functions: oracle samples exact {vf['oracle_sample_exact']} / "
                 f"{vf['multi_background']['oracle_sample_exact']}")
+    # every headline instance against the closed form of its game (path
+    # products / unanimity terms): FP32 result, and the secondary elementwise
+    # error over the outputs with |E| >= 1e-3 max |E|
+    if errs is not None and args.closed_form:
+        from concurrent.futures import ThreadPoolExecutor
+        from oracle import closed_forms as CF
+
+        def cf_ref(i):
+            g = games.d20_batch_instance(i)[0]
+            m_, c_ = CF.tree_mobius_sparse(g) if i % 2 == 0 else CF.planted_mobius_sparse(g)
+            return CF.fsi_from_sparse_mobius(m_, c_, d, l)
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            cfr = list(ex.map(cf_ref, range(n)))
+        nw = np.array([normwise(res32[i * M:(i + 1) * M], cfr[i]) for i in range(n)])
+        ew = np.array([elementwise(res32[i * M:(i + 1) * M], cfr[i]) for i in range(n)])
+        errs.update({"vs_closed_form_max": float(nw.max()),
+                     "vs_closed_form_median": float(np.median(nw)),
+                     "vs_closed_form_max_tree": float(nw[0::2].max()),
+                     "vs_closed_form_max_planted": float(nw[1::2].max()),
+                     "vs_closed_form_instances": n,
+                     "elementwise_vs_closed_form_max": float(ew.max()),
+                     "elementwise_vs_closed_form_median": float(np.median(ew)),
+                     "closed_form_note": "FP64 closed form of each game; the FP32 error "
+                                         "includes the rounding of the inputs to FP32"})
+        log(f"closed forms of all {n} instances in {time.perf_counter() - t0:.1f}s: "
+            f"normwise max {nw.max():.3e} median {np.median(nw):.3e}, elementwise max {ew.max():.3e}")
+    if ragged is not None:
+        rc = ragged_ctx
+        t0 = time.perf_counter()
+
+        def rag_err(i):
+            v = rc["v32"][rc["voff"][i]:rc["voff"][i + 1]].astype(np.float64)
+            ref = oracle.fsi_c(v, rc["ds"][i], rc["ls"][i], nthreads=1)
+            return normwise(rc["out"][rc["ooff"][i]:rc["ooff"][i + 1]], ref)
+
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            rerr = np.array(list(ex.map(rag_err, range(len(rc["ds"])))))
+        ragged["vs_oracle_max"] = float(rerr.max())
+        ragged["vs_oracle_median"] = float(np.median(rerr))
+        ragged["vs_oracle_instances"] = int(rerr.size)
+        log(f"ragged batch vs oracle (all {rerr.size}): max {rerr.max():.3e} "
+            f"({time.perf_counter() - t0:.1f}s)")
+    if c3 is not None:
+        for l3 in (2, 4):
+            refs = {"tree64": oracle.fsi_c(c3_ctx["tree"], 20, l3, nthreads=threads),
+                    "tree32": oracle.fsi_c(c3_ctx["tree"].astype(np.float32).astype(np.float64),
+                                           20, l3, nthreads=threads),
+                    "pm1": oracle.fsi_exact_int(c3_ctx["pm1"], 20, l3, nthreads=threads)}
+            for vname in ("tree", "pm1"):
+                for form in ("f64", "f32_fp64mob", "f32_compensated", "f32"):
+                    ref = refs["pm1"] if vname == "pm1" else (
+                        refs["tree64"] if form == "f64" else refs["tree32"])
+                    c3[f"l{l3}_{vname}_{form}"] = normwise(c3_ctx["got"][(l3, vname, form)], ref)
+        log(f"d=20 errors vs oracle: {c3}")
     cpu = None
     if args.cpu_sample > 0:
         k = min(args.cpu_sample, n)
@@ -540,11 +693,27 @@ def main():
         for i in range(k):
             oracle.fsi_c(vals64[i * N:(i + 1) * N], d, l, nthreads=threads)
         el = time.perf_counter() - t0
+        # one instance on one core, split into the Moebius butterfly and the
+        # brute-force superset sums
+        v0 = vals64[:N]
+        t1 = time.perf_counter()
+        oracle.mobius_c(v0)
+        mob_s = time.perf_counter() - t1
+        t1 = time.perf_counter()
+        oracle.fsi_c(v0, d, l, nthreads=1)
+        one_s = time.perf_counter() - t1
         cpu = {"value": k * N / el, "unit": "coalition-values/s", "cores": threads,
                "kind": "oracle",
                "sample": f"{k} of the {n} instances (d=20, l=4, FP64 C oracle: Moebius "
-                         f"butterfly + brute-force superset sums), {el:.1f} s"}
-        log(f"cpu oracle: {cpu['value']:.3e} values/s on {threads} threads")
+                         f"butterfly + brute-force superset sums), {el:.1f} s",
+               "cpu_model": cpu_model(),
+               "one_core": {"instance_s": one_s, "mobius_s": mob_s,
+                            "superset_sums_s": max(0.0, one_s - mob_s),
+                            "values_per_s": N / one_s,
+                            "what": "instance 0 on one thread: the whole oracle, its Moebius "
+                                    "butterfly alone, and the difference (superset sums)"}}
+        log(f"cpu oracle: {cpu['value']:.3e} values/s on {threads} threads; one core "
+            f"{one_s:.2f} s per instance (Moebius {mob_s:.3f} s)")
 
     wkey = f"{n}x(d={d},l={l}) {args.precision} algo={args.algo} tile_bits={args.tile_bits}"
     traffic = measured_traffic(wkey)
@@ -590,6 +759,8 @@ def main():
         "indices": indices,
         "value_function": vfun,
         "large_instances": large,
+        "ragged": ragged,
+        "single_d20": c3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

@@ -436,6 +436,17 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     for (int l = 1; l <= kFastMaxL; ++l) { lbeg[l] = acc; acc += cnt[l]; }
     lbeg[kFastMaxL + 1] = acc;
   }
+  // several orders run as one launch over all items (the kernel dispatches
+  // per item): the costliest items first (higher order, then more values),
+  // so the persistent grid ends evenly
+  int n_orders = 0;
+  for (int l = 1; l <= kFastMaxL; ++l) n_orders += lbeg[l + 1] > lbeg[l];
+  if (n_orders > 1)
+    std::stable_sort(fitems.begin(), fitems.end(), [&](const FastItem& x, const FastItem& y) {
+      const int lx = item_l(x), ly = item_l(y);
+      if (lx != ly) return lx > ly;
+      return (x.te - x.tb) > (y.te - y.tb);
+    });
 
   // every tile of every instance (standalone Moebius low pass)
   std::vector<TileItem> all_tiles;
@@ -647,11 +658,18 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       if (F.ngroups > 1) a.fast.grouped[F.l] = 1;
       if (F.mobius_in) a.fast.mobius_in = 1;
     }
+    int wgs = 1;
+    a.fast.lds_mixed = 0;
     for (int l = 0; l <= kFastMaxL; ++l) {
       a.fast.lds[l] = fast_lds[l];
       const int nl = l >= 1 ? lbeg[l + 1] - lbeg[l] : 0;
       a.fast.grid[l] = nl > 0 ? std::max(1, std::min(nl, n_cu * fast_wgs_per_cu(prec, l))) : 0;
+      if (nl > 0) {
+        wgs = std::max(wgs, fast_wgs_per_cu(prec, l));
+        a.fast.lds_mixed = std::max(a.fast.lds_mixed, fast_lds[l]);
+      }
     }
+    a.fast.grid_mixed = std::max(1, std::min((int)fitems.size(), n_cu * wgs));
   }
   P->sched.autotuned = 0;
   P->sched.fast_instances = 0;

@@ -43,6 +43,8 @@ struct FastLaunch {
   int grid[kFastMaxL + 1];
   size_t lds[kFastMaxL + 1];
   int grouped[kFastMaxL + 1];     // 1: an instance of this order has several output groups
+  int grid_mixed;                 // grid of the one launch over every order's items
+  size_t lds_mixed;               // its dynamic LDS (the largest order's)
   int mobius_in;                  // 1: the input is already the Moebius transform
   const void* vals32;
   const void* vals64;
@@ -53,6 +55,11 @@ struct FastLaunch {
 // lds[l]: dynamic LDS of the order-l kernel, 0 = not used by the plan.
 hipError_t configure_fast(int prec, const size_t* lds);
 hipError_t launch_fast_group(const FastLaunch& f, int l, hipStream_t st);
+// One launch over the items of every order (plans with more than one order).
+hipError_t launch_fast_mixed(const FastLaunch& f, hipStream_t st);
+// Register-phase launches of one apply: 0, or 1 (one order, or several
+// orders in one mixed launch).
+int fast_launches(const FastLaunch& f);
 // Orders l with work items, ascending; returns their number.
 int fast_groups(const FastLaunch& f, int* ls);
 bool fast_supported(int prec);

@@ -441,7 +441,7 @@ int num_stages(const LaunchArgs& a) {
   //        [generic reduce], [wide gather, wide final], [register-phase reduce]
   // two-pass: Moebius low pass, high passes, tile, reduce
   if (a.algo == ALGO_FUSED)
-    return fast_groups(a.fast, nullptr) + (a.n_tile_items > 0) + (a.n_generic > 0) +
+    return fast_launches(a.fast) + (a.n_tile_items > 0) + (a.n_generic > 0) +
            2 * (a.n_wide_items > 0) + (a.n_red_chunks > 0);
   return 3 + a.n_mob_passes;
 }
@@ -488,11 +488,11 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   if (a.algo == ALGO_FUSED) {
     int ls[kFastMaxL];
     const int ng = fast_groups(a.fast, ls);
-    if (stage < ng) {
+    if (stage < fast_launches(a.fast)) {
       FastLaunch f = a.fast;
       f.vals32 = a.values;
       f.vals64 = a.values;
-      return launch_fast_group(f, ls[stage], st);
+      return ng > 1 ? launch_fast_mixed(f, st) : launch_fast_group(f, ls[0], st);
     }
   }
   if (a.algo == ALGO_FUSED) {

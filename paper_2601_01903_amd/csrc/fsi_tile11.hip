@@ -252,6 +252,19 @@ struct Lds {
   static constexpr int zeros = 128;
   static constexpr int bytes = reg1 + reg2 + reg3 + zeros;
 };
+// The zero row sits at one offset past the regions of every order, so one
+// kernel can run items of different orders (each item uses its order's
+// regions below that offset) and the row is written once per workgroup.
+template <typename SwT, typename MobT>
+struct LdsAll {
+  static constexpr int zoff =
+      imax2(imax2(Lds<1, SwT, MobT>::reg1 + Lds<1, SwT, MobT>::reg2 + Lds<1, SwT, MobT>::reg3,
+                  Lds<2, SwT, MobT>::reg1 + Lds<2, SwT, MobT>::reg2 + Lds<2, SwT, MobT>::reg3),
+            imax2(Lds<3, SwT, MobT>::reg1 + Lds<3, SwT, MobT>::reg2 + Lds<3, SwT, MobT>::reg3,
+                  Lds<4, SwT, MobT>::reg1 + Lds<4, SwT, MobT>::reg2 + Lds<4, SwT, MobT>::reg3));
+  static constexpr int zeros = 128;
+  static constexpr int bytes = zoff + zeros;
+};
 
 // ------------------------------------------------------------ weight core
 // The weights of the tile's |U_H| sit in LDS (lam), read at wave-uniform
@@ -518,7 +531,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   SwT* S1 = reinterpret_cast<SwT*>(smem + LD::reg1);
   SwT* Z = reinterpret_cast<SwT*>(smem + LD::reg1);
   double* lamL = reinterpret_cast<double*>(smem + LD::reg1 + LD::reg2);
-  const SwT* zrow = reinterpret_cast<const SwT*>(smem + LD::reg1 + LD::reg2 + LD::reg3);
+  const SwT* zrow = reinterpret_cast<const SwT*>(smem + LdsAll<SwT, MobT>::zoff);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -762,9 +775,9 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
               const int32_t* __restrict__ torder, double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char smem[];
   {
-    using LD = Lds<L, SwT, MobT>;
-    uint32_t* z = reinterpret_cast<uint32_t*>(smem + LD::reg1 + LD::reg2 + LD::reg3);
-    if (threadIdx.x < LD::zeros / 4) z[threadIdx.x] = 0u;
+    using LA = LdsAll<SwT, MobT>;
+    uint32_t* z = reinterpret_cast<uint32_t*>(smem + LA::zoff);
+    if (threadIdx.x < LA::zeros / 4) z[threadIdx.x] = 0u;
     __syncthreads();
   }
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -776,12 +789,43 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
   }
 }
 
+// Items of every order in one launch (a batch of instances with different
+// l): each item runs the code compiled for its instance's order; the
+// regions of all orders share one allocation (LdsAll). Order-4 items use the
+// grouped code when GROUPED4 is set.
+template <typename SwT, typename MobT, bool IN64, int WPE, bool GROUPED4, bool MOBIN>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
+tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
+                    const FastItem* __restrict__ items, int n_items,
+                    const float* __restrict__ vals32, const double* __restrict__ vals64,
+                    const int32_t* __restrict__ torder, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  {
+    using LA = LdsAll<SwT, MobT>;
+    uint32_t* z = reinterpret_cast<uint32_t*>(smem + LA::zoff);
+    if (threadIdx.x < LA::zeros / 4) z[threadIdx.x] = 0u;
+    __syncthreads();
+  }
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const FastItem W = items[item];
+    const InstDev I = insts[W.inst];
+    const FastClassDev* C = classes + I.fcls;
+    const int l = __builtin_amdgcn_readfirstlane(C->l);
+    switch (l) {
+      case 1: run_item<1, SwT, MobT, IN64, false, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 2: run_item<2, SwT, MobT, IN64, false, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 3: run_item<3, SwT, MobT, IN64, false, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      default: run_item<4, SwT, MobT, IN64, GROUPED4, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+    }
+    __syncthreads();
+  }
+}
+
+// Every order's kernel places the zero row past the regions of all orders
+// (LdsAll), so each allocates the same size.
 template <typename SwT, typename MobT>
-constexpr int lds_bytes_for(int L) {
-  return L == 1 ? Lds<1, SwT, MobT>::bytes
-       : L == 2 ? Lds<2, SwT, MobT>::bytes
-       : L == 3 ? Lds<3, SwT, MobT>::bytes
-                : Lds<4, SwT, MobT>::bytes;
+constexpr int lds_bytes_for(int) {
+  return LdsAll<SwT, MobT>::bytes;
 }
 
 }  // namespace t11
@@ -833,6 +877,42 @@ static hipError_t config_t11(size_t lds) {
   return config_t11_m<L, SwT, MobT, IN64, true>(lds);
 }
 
+// One launch over the items of every order (the plan has several orders).
+template <typename SwT, typename MobT, bool IN64, bool MOBIN>
+static hipError_t launch_mixed_m(const FastLaunch& f, hipStream_t st) {
+  auto k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
+  if (f.grouped[kFastMaxL]) k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>;
+  hipLaunchKernelGGL(k, dim3(f.grid_mixed), dim3(t11::NT), f.lds_mixed, st, f.classes, f.insts,
+                     f.items, f.n_items, static_cast<const float*>(f.vals32),
+                     static_cast<const double*>(f.vals64), f.torder, f.partial);
+  return hipGetLastError();
+}
+
+template <typename SwT, typename MobT, bool IN64>
+static hipError_t launch_mixed_t(const FastLaunch& f, hipStream_t st) {
+  return f.mobius_in ? launch_mixed_m<SwT, MobT, IN64, true>(f, st)
+                     : launch_mixed_m<SwT, MobT, IN64, false>(f, st);
+}
+
+template <typename SwT, typename MobT, bool IN64, bool MOBIN>
+static hipError_t config_mixed_m(size_t lds) {
+  for (int g = 0; g < 2; ++g) {
+    auto k = g ? t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>
+               : t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename SwT, typename MobT, bool IN64>
+static hipError_t config_mixed_t(size_t lds) {
+  hipError_t e = config_mixed_m<SwT, MobT, IN64, false>(lds);
+  if (e != hipSuccess) return e;
+  return config_mixed_m<SwT, MobT, IN64, true>(lds);
+}
+
 template <typename SwT, typename MobT, bool IN64>
 static hipError_t launch_group_t(const FastLaunch& f, int l, hipStream_t st) {
   switch (l) {
@@ -847,6 +927,11 @@ static hipError_t launch_group_t(const FastLaunch& f, int l, hipStream_t st) {
 template <typename SwT, typename MobT, bool IN64>
 static hipError_t config_all_t(const size_t* lds) {
   hipError_t e = hipSuccess;
+  size_t mx = 0;
+  int orders = 0;
+  for (int l = 1; l <= kFastMaxL; ++l)
+    if (lds[l]) { mx = std::max(mx, lds[l]); ++orders; }
+  if (orders > 1 && (e = config_mixed_t<SwT, MobT, IN64>(mx)) != hipSuccess) return e;
   if (lds[1] && (e = config_t11<1, SwT, MobT, IN64>(lds[1])) != hipSuccess) return e;
   if (lds[2] && (e = config_t11<2, SwT, MobT, IN64>(lds[2])) != hipSuccess) return e;
   if (lds[3] && (e = config_t11<3, SwT, MobT, IN64>(lds[3])) != hipSuccess) return e;
@@ -860,6 +945,16 @@ hipError_t configure_fast(int prec, const size_t* lds) {
     case PREC_F32_COMP: return config_all_t<float, t11::TwoF, false>(lds);
     case PREC_F32_FP64MOB: return config_all_t<float, double, false>(lds);
     case PREC_F64: return config_all_t<double, double, true>(lds);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fast_mixed(const FastLaunch& f, hipStream_t st) {
+  switch (f.prec) {
+    case PREC_F32: return launch_mixed_t<float, float, false>(f, st);
+    case PREC_F32_COMP: return launch_mixed_t<float, t11::TwoF, false>(f, st);
+    case PREC_F32_FP64MOB: return launch_mixed_t<float, double, false>(f, st);
+    case PREC_F64: return launch_mixed_t<double, double, true>(f, st);
   }
   return hipErrorInvalidValue;
 }
@@ -882,6 +977,11 @@ int fast_groups(const FastLaunch& f, int* ls) {
       ++n;
     }
   return n;
+}
+
+int fast_launches(const FastLaunch& f) {
+  const int g = fast_groups(f, nullptr);
+  return g > 1 ? 1 : g;
 }
 
 bool fast_supported(int prec) {
