@@ -21,8 +21,9 @@ struct MobItem {
 
 // Register-phase kernel (fsi_tile11.hip)
 constexpr int kFastThreads = 256;
-constexpr int kFastKmax = 27;      // output slots per thread
-constexpr int kFastMetaStride = 28;  // per-thread metadata words (7 x 16 bytes)
+constexpr int kFastRuns = 14;      // gather positions (runs of two outputs) per thread
+constexpr int kFastKmax = 2 * kFastRuns;  // output slots per thread
+constexpr int kFastMetaStride = 16;  // per-thread metadata words (4 x 16 bytes)
 constexpr int kFastTileBits = 11;
 constexpr int kFastMaxL = 4;
 

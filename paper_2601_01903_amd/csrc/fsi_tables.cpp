@@ -281,13 +281,11 @@ int fast_max_high_bits(int l) {
 int fast_output_slots(int d, int l) {
   if (d < t11::B || l > 4 || l > d) return -1;
   const int h = d - t11::B;
-  int slots = 0;
-  for (int sL = 0; sL <= l; ++sL) {
-    int64_t n = 0;
-    for (int sH = 0; sH <= std::min(l - sL, h); ++sH) n += binom(t11::B, sL) * binom(h, sH);
-    slots += (int)((n + kFastThreads - 1) / kFastThreads);
-  }
-  return slots;
+  const int64_t pos = t11::positions_needed(l, h);
+  // only order 4 gathers its outputs in several groups
+  if (l < 4 && pos > t11::np_order(l)) return -1;
+  if (pos > (int64_t)1 << 20) return -1;
+  return (int)(2 * pos);
 }
 
 std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
@@ -338,50 +336,81 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
                 C.lam[(size_t)u * C.lam_ublock + C.lam_soff[sL] + slot * (b + 1) + sL + r];
         }
     }
-  // outputs: slots grouped by |S_L| (descending), each output of a group
-  // at (slot kb + q / 256, thread q % 256) for its q-th position in
-  // canonical order. A slot holds 256 outputs of one |S_L|; consecutive
-  // slots go to one output group until it has kFastKmax of them (each group
-  // is gathered by its own work items over every tile).
-  const size_t M = C.out_masks.size();
-  const uint32_t lowmask = (1u << b) - 1;
-  std::vector<std::vector<uint32_t>> byl(l + 1);
-  for (size_t k = 0; k < M; ++k) byl[popc(C.out_masks[k] & lowmask)].push_back((uint32_t)k);
+  // outputs: runs of two outputs (S_L of ranks 2r and 2r + 1 among the S_L
+  // of one size, one S_H). Runs are taken by |S_L| (descending), then S_H,
+  // then r, and dealt to wave units: unit u is position u / 4 of wave u % 4
+  // of the workgroup, 64 runs of one |S_L| (so the j-stride is uniform in a
+  // wave); a unit left short by its |S_L| is filled with dummy runs (offset
+  // 0, S_H = 0: a valid read whose sums nothing uses). Output group g takes
+  // the units of positions [g kRuns, (g + 1) kRuns).
   const int total = fast_output_slots(C.d, l);
   if (total < 0) return "register-phase kernel does not apply";
-  F->ngroups = (total + kFastKmax - 1) / kFastKmax;
+  const int npos = total / 2;
+  F->ngroups = (npos + kRuns - 1) / kRuns;
   // only order 4 has a grouped kernel instantiation
   if (F->ngroups > 1 && l != kFastMaxL) return "output groups are only built for l = 4";
+  if (kRuns != kFastRuns) return "gather position count mismatch";
+  const size_t M = C.out_masks.size();
+  const uint32_t lowmask = (1u << b) - 1;
+  std::map<uint64_t, int> canon;
+  for (size_t k = 0; k < M; ++k) canon[C.out_masks[k]] = (int)k;
+  // S_L of each size in colex rank order
+  std::vector<std::vector<uint32_t>> low(l + 1);
+  for (uint32_t m = 0; m <= lowmask; ++m) {
+    const int sL = popc(m);
+    if (sL <= l) low[sL].push_back(m);
+  }
+  for (int sL = 0; sL <= l; ++sL) {
+    std::sort(low[sL].begin(), low[sL].end(),
+              [](uint32_t x, uint32_t y) { return rank_colex(x) < rank_colex(y); });
+    if ((int)low[sL].size() != cbinom(B, sL)) return "low output count mismatch";
+  }
+  // S_H of each size
+  std::vector<std::vector<uint32_t>> high(l + 1);
+  for (uint32_t m = 0; m < (1u << h); ++m) {
+    const int sH = popc(m);
+    if (sH <= l) high[sH].push_back(m);
+  }
   F->meta.assign((size_t)F->ngroups * kFastThreads * kFastMetaStride, 0u);
-  F->gs8.assign((size_t)F->ngroups * kFastMetaStride, 0u);
+  F->gs8.assign((size_t)F->ngroups * kRuns * 4, 0u);
   F->gnkk.assign(F->ngroups, 0);
   F->pidx.assign(M, -1);
   F->pgroup.assign(M, -1);
-  int slot = 0;   // running slot over all groups
+  int64_t unit = 0;
   for (int sL = l; sL >= 0; --sL) {
-    const std::vector<uint32_t>& ks = byl[sL];
-    const int nslot = (int)((ks.size() + kFastThreads - 1) / kFastThreads);
-    for (int q = 0; q < nslot; ++q) {
-      const int g = (slot + q) / kFastKmax, kk = (slot + q) % kFastKmax;
-      F->gs8[(size_t)g * kFastMetaStride + kk] = (uint32_t)cbinom(B, sL) * 8u;
-      F->gnkk[g] = std::max(F->gnkk[g], kk + 1);
-    }
-    for (size_t q = 0; q < ks.size(); ++q) {
-      const uint32_t S = C.out_masks[ks[q]];
-      const uint32_t SL = S & lowmask, SH = S >> b;
-      const int sH = popc(SH);
-      const uint32_t A = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) + rank_colex(SL));
-      const int gs = slot + (int)(q / kFastThreads), t = (int)(q % kFastThreads);
-      const int g = gs / kFastKmax, kk = gs % kFastKmax;
-      if (A * 8 >= (1u << F->mshift) || (uint64_t)SH >= (1ull << (32 - F->mshift)))
-        return "output metadata overflow";
-      F->meta[((size_t)g * kFastThreads + t) * kFastMetaStride + kk] = (A * 8) | (SH << F->mshift);
-      F->pidx[ks[q]] = kk * kFastThreads + t;
-      F->pgroup[ks[q]] = g;
-    }
-    slot += nslot;
+    const uint32_t nr = (uint32_t)cbinom(B, sL);
+    int lane = 64;   // start a new unit for each |S_L|
+    for (int sH = 0; sH <= std::min(l - sL, h); ++sH)
+      for (uint32_t SH : high[sH])
+        for (uint32_t r0 = 0; r0 < nr; r0 += 2) {
+          if (lane == 64) {
+            lane = 0;
+            ++unit;
+          }
+          const int64_t u = unit - 1;
+          const int pos = (int)(u / 4), w = (int)(u % 4);
+          const int g = pos / kRuns, p = pos % kRuns, t = 64 * w + lane;
+          if (g >= F->ngroups) return "gather unit past the last group";
+          F->gs8[((size_t)g * kRuns + p) * 4 + w] = (uint32_t)nrp(sL) * 8u;
+          F->gnkk[g] = std::max(F->gnkk[g], 2 * (p + 1));
+          const uint32_t A =
+              (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * nrp(sL) + (int)r0);
+          if (A * 8 >= (1u << F->mshift) || (uint64_t)SH >= (1ull << (32 - F->mshift)))
+            return "output metadata overflow";
+          F->meta[((size_t)g * kFastThreads + t) * kFastMetaStride + p] = (A * 8) | (SH << F->mshift);
+          for (uint32_t e = 0; e < 2; ++e) {
+            if (r0 + e >= nr) break;
+            const uint32_t S = low[sL][r0 + e] | (SH << b);
+            auto it = canon.find(S);
+            if (it == canon.end()) return "run output outside the canonical set";
+            F->pidx[it->second] = (int)(2 * p + e) * kFastThreads + t;
+            F->pgroup[it->second] = g;
+          }
+          ++lane;
+        }
   }
-  if (slot != total) return "output slot count mismatch";
+  for (size_t k = 0; k < M; ++k)
+    if (F->pidx[k] < 0) return "an output has no run";
   F->nkk = 0;
   for (int g = 0; g < F->ngroups; ++g) F->nkk = std::max(F->nkk, F->gnkk[g]);
   return "";

@@ -181,13 +181,35 @@ constexpr int zrow_of(int L, uint32_t SL) {
 }
 
 // ---- Y ----
+// Group (s_L, slot) holds the S_L of size s_L in rank order, padded to an
+// even count so that every pair of ranks (2r, 2r + 1) is one aligned
+// 16-byte read of the gather.
 constexpr int nslots(int L, int s) { return s > L ? 0 : (L - s + 1) * (L - s + 2) / 2; }
+constexpr int nrp(int s) { return (cbinom(B, s) + 1) & ~1; }
 constexpr int ybase(int L, int s) {
   int o = 0;
-  for (int q = 0; q < s; ++q) o += nslots(L, q) * cbinom(B, q);
+  for (int q = 0; q < s; ++q) o += nslots(L, q) * nrp(q);
   return o;
 }
 constexpr int ysize(int L) { return ybase(L, L + 1); }
+
+// ---- cross-tile gather ----
+// A run is two outputs (S_L of ranks 2r and 2r + 1 among the S_L of one
+// size, one S_H): one popcount |S_H & U_H| and one 16-byte read of Y per
+// tile. A thread holds up to kFastRuns runs ("positions"); at each position
+// the 64 runs of a wave share s_L, so the j-stride of Y is wave-uniform.
+// Runs of one (s_L, S_H) for the outputs of order L with h high bits:
+constexpr int64_t runs_of(int L, int h, int sL) {
+  int64_t nh = 0;
+  for (int sH = 0; sH <= L - sL && sH <= h; ++sH) nh += cbinom(h, sH);
+  return (int64_t)((cbinom(B, sL) + 1) / 2) * nh;
+}
+// positions of 4 waves x 64 runs the outputs need (all groups together)
+constexpr int64_t positions_needed(int L, int h) {
+  int64_t units = 0;
+  for (int sL = 0; sL <= L; ++sL) units += (runs_of(L, h, sL) + 63) / 64;
+  return (units + 3) / 4;
+}
 
 // ---- final-core weights (FP64, global memory), per high popcount u:
 // entry (s_L, slot, r) at lamoff(s_L) + slot * 12 + r (zero for r > 11 - s_L) ----
@@ -221,6 +243,19 @@ constexpr int meta_shift(int L) {
   return s;
 }
 constexpr int kMaxH = 32 - meta_shift(3);
+
+// gather positions per thread; the kernel of order L unrolls np_order(L) of
+// them (the most its outputs need at any h the metadata word holds, at most
+// kRuns; past that only order 4 splits its outputs into groups)
+constexpr int kRuns = 14;
+constexpr int np_order(int L) {
+  int64_t m = 0;
+  for (int h = 0; h <= 32 - meta_shift(L); ++h) {
+    const int64_t p = positions_needed(L, h);
+    m = p > m ? p : m;
+  }
+  return m > kRuns ? kRuns : (int)m;
+}
 
 }  // namespace t11
 }  // namespace fsi

@@ -297,7 +297,7 @@ __device__ __forceinline__ void row_task(int chunk, int lane, const SwT* Z, doub
   }
   if (ok) {
 #pragma unroll
-    for (int k = K0; k < K1; ++k) Y[YB + k * NR + row] = a[k - K0];
+    for (int k = K0; k < K1; ++k) Y[YB + k * nrp(S) + row] = a[k - K0];
   }
 }
 
@@ -311,10 +311,10 @@ __device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double*
   const int p = ok ? p0 : 0;
   int zrow, lofs, yidx;
   if (p < N0) {
-    zrow = 0; lofs = K<L>::LAM0 + p * ZROW; yidx = K<L>::YB0 + p;
+    zrow = 0; lofs = K<L>::LAM0 + p * ZROW; yidx = K<L>::YB0 + p * nrp(0);
   } else {
     const int row = (p - N0) / N1, slot = (p - N0) - row * N1;
-    zrow = 1 + row; lofs = K<L>::LAM1 + slot * ZROW; yidx = K<L>::YB1 + slot * B + row;
+    zrow = 1 + row; lofs = K<L>::LAM1 + slot * ZROW; yidx = K<L>::YB1 + slot * nrp(1) + row;
   }
   const SwT* zr = Z + zrow * ZROW;
   const double2* lw = reinterpret_cast<const double2*>(lam + lofs);
@@ -522,7 +522,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
                                          const double* __restrict__ vals64,
                                          const int32_t* __restrict__ torder,
                                          double* __restrict__ partial, unsigned char* smem) {
-  constexpr int KMAX = kFastKmax;
+  static_assert(kFastRuns == kRuns, "gather positions");
+  constexpr int NP = np_order(L);     // gather positions of this order
+  constexpr int KMAX = 2 * NP;        // output slots
   constexpr int LB = K<L>::LB;
   using LD = Lds<L, SwT, MobT>;
   MobT* R = reinterpret_cast<MobT*>(smem);
@@ -561,7 +563,8 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const int grp = GROUPED ? __builtin_amdgcn_readfirstlane(W.group) : 0;
   const uint4* meta_g =
       reinterpret_cast<const uint4*>(C->meta + ((size_t)grp * NT + tid) * kFastMetaStride);
-  const cdptr_u gs8 = (cdptr_u)(C->gs8 + grp * kFastMetaStride);
+  // j-stride of Y per (position, wave)
+  const cdptr_u gs8 = (cdptr_u)(C->gs8 + (grp * kRuns) * 4 + wave);
   const int nkk = GROUPED ? C->gnkk[grp] : C->nkk;
   // input already Moebius-transformed (a separate instantiation): the
   // butterflies are skipped
@@ -716,9 +719,9 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     // prefetch the next tile and this tile's output metadata while the
     // weight core runs
     if (k + 1 < W.te) load_tile(UHn);
-    uint32_t meta[kFastMetaStride];
+    uint32_t meta[(NP + 3) & ~3];
 #pragma unroll
-    for (int q = 0; q < kFastMetaStride / 4; ++q) {
+    for (int q = 0; q < (NP + 3) / 4; ++q) {
       const uint4 v = meta_g[q];
       meta[4 * q] = v.x; meta[4 * q + 1] = v.y; meta[4 * q + 2] = v.z; meta[4 * q + 3] = v.w;
     }
@@ -732,25 +735,30 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     }
     __syncthreads();
     // ---- cross-tile sum: E_S += Y[S_L, s_H, |S_H & U_H|] ----
-    // slot kk holds outputs of one |S_L|: the j-stride gs8[kk] is uniform
+    // position p holds a run of two outputs (ranks 2r, 2r + 1 of one |S_L|,
+    // one S_H): one popcount and one 16-byte read; the j-stride is uniform
+    // in the wave
     {
       const uint32_t UHs = (uint32_t)UH << mshift;
       const unsigned char* Yb = reinterpret_cast<const unsigned char*>(Y);
-      constexpr int GB = 9;   // outputs per batch of reads
+      constexpr int GB = 5;   // runs per batch of reads
 #pragma unroll
-      for (int k0 = 0; k0 < KMAX; k0 += GB) {
-        double v[GB];
+      for (int p0 = 0; p0 < NP; p0 += GB) {
+        double2 v[GB];
 #pragma unroll
         for (int q = 0; q < GB; ++q) {
-          if (k0 + q < KMAX) {
-            const uint32_t m = meta[k0 + q];
-            const uint32_t off = (m & omask) + (uint32_t)__popc(m & UHs) * gs8[k0 + q];
-            v[q] = *reinterpret_cast<const double*>(Yb + off);
+          if (p0 + q < NP) {
+            const uint32_t m = meta[p0 + q];
+            const uint32_t off = (m & omask) + (uint32_t)__popc(m & UHs) * gs8[(p0 + q) * 4];
+            v[q] = *reinterpret_cast<const double2*>(Yb + off);
           }
         }
 #pragma unroll
         for (int q = 0; q < GB; ++q)
-          if (k0 + q < KMAX) acc[k0 + q] += v[q];
+          if (p0 + q < NP) {
+            acc[2 * (p0 + q)] += v[q].x;
+            acc[2 * (p0 + q) + 1] += v[q].y;
+          }
       }
     }
     UH = UHn;

@@ -92,15 +92,15 @@ int main() {
       e = build_fast_class(C, &F);
       CHECK(e.empty(), "d=%d l=%d build_fast_class: %s", d, l, e.c_str());
       if (!e.empty()) continue;
-      CHECK(F.ngroups == (slots + kFastKmax - 1) / kFastKmax, "d=%d l=%d: %d output groups", d, l,
-            F.ngroups);
-      int sum = 0;
-      for (int g = 0; g < F.ngroups; ++g) {
-        CHECK(F.gnkk[g] >= 1 && F.gnkk[g] <= kFastKmax, "d=%d l=%d group %d: %d slots", d, l, g,
-              F.gnkk[g]);
-        sum += F.gnkk[g];
-      }
-      CHECK(sum == slots, "d=%d l=%d: %d slots over the groups, %d needed", d, l, sum, slots);
+      // runs of two outputs: 2 slots per gather position, kRuns positions per group
+      const int npos = slots / 2;
+      CHECK(slots % 2 == 0 && npos == positions_needed(l, d - 11), "d=%d l=%d: %d slots", d, l, slots);
+      CHECK(F.ngroups == (npos + kRuns - 1) / kRuns, "d=%d l=%d: %d output groups", d, l, F.ngroups);
+      CHECK(l == 4 || npos <= np_order(l), "d=%d l=%d: %d positions, kernel unrolls %d", d, l, npos,
+            np_order(l));
+      for (int g = 0; g < F.ngroups; ++g)
+        CHECK(F.gnkk[g] >= 2 && F.gnkk[g] <= 2 * kRuns && F.gnkk[g] % 2 == 0,
+              "d=%d l=%d group %d: %d slots", d, l, g, F.gnkk[g]);
       const uint32_t omask = (1u << F.mshift) - 1u;
       std::set<int> used;
       for (size_t k = 0; k < C.out_masks.size(); ++k) {
@@ -110,21 +110,35 @@ int main() {
         CHECK(p >= 0 && p < F.gnkk[g] * kFastThreads, "d=%d l=%d output %zu: slot out of range", d, l, k);
         CHECK(used.insert(g * kFastKmax * kFastThreads + p).second, "d=%d l=%d: slot used twice", d, l);
         const int kk = p / kFastThreads, t = p % kFastThreads;
-        const uint32_t m = F.meta[((size_t)g * kFastThreads + t) * kFastMetaStride + kk];
+        const int pos = kk / 2, e = kk % 2, w = t / 64;
+        const uint32_t m = F.meta[((size_t)g * kFastThreads + t) * kFastMetaStride + pos];
         const uint32_t S = C.out_masks[k];
         const uint32_t SL = S & 0x7FFu, SH = S >> 11;
         CHECK((m >> F.mshift) == SH, "d=%d l=%d output %zu: S_H decodes wrongly", d, l, k);
-        // the Y offset at j = 0 addresses (S_L, s_H): its group base plus the
-        // rank of S_L, in units of the group's row count
+        // the run's Y offset at j = 0 addresses (S_L of the even rank, s_H):
+        // group base plus the pair's first rank; this output is element e
         const int sL = cpop((int)SL), sH = cpop((int)SH);
-        const uint32_t want = (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * cbinom(B, sL) +
-                                         rank_colex(SL)) * 8u;
+        const int rk = rank_colex(SL);
+        CHECK(rk % 2 == e, "d=%d l=%d output %zu: rank parity %d in element %d", d, l, k, rk, e);
+        const uint32_t want =
+            (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * nrp(sL) + rk - e) * 8u;
         CHECK((m & omask) == want, "d=%d l=%d output %zu: Y offset decodes wrongly", d, l, k);
-        const uint32_t gs = F.gs8[(size_t)g * kFastMetaStride + kk];
-        CHECK(gs == (uint32_t)cbinom(B, sL) * 8u, "d=%d l=%d: j stride of slot %d", d, l, kk);
-        CHECK((m & omask) + (uint32_t)sH * gs < (uint32_t)ysize(l) * 8u,
-              "d=%d l=%d output %zu: Y offset past the tile's results", d, l, k);
+        CHECK(want % 16 == 0, "d=%d l=%d output %zu: read not 16-byte aligned", d, l, k);
+        const uint32_t gs = F.gs8[((size_t)g * kRuns + pos) * 4 + w];
+        CHECK(gs == (uint32_t)nrp(sL) * 8u, "d=%d l=%d: j stride of position %d wave %d", d, l, pos, w);
+        CHECK((m & omask) + (uint32_t)sH * gs + 16 <= (uint32_t)ysize(l) * 8u,
+              "d=%d l=%d output %zu: Y read past the tile's results", d, l, k);
       }
+      // every run's read (real or dummy) stays inside Y for every j
+      for (int g = 0; g < F.ngroups; ++g)
+        for (int t = 0; t < kFastThreads; ++t)
+          for (int pos = 0; pos < kRuns; ++pos) {
+            const uint32_t m = F.meta[((size_t)g * kFastThreads + t) * kFastMetaStride + pos];
+            const uint32_t gs = F.gs8[((size_t)g * kRuns + pos) * 4 + t / 64];
+            const int sH = cpop((int)(m >> F.mshift));
+            CHECK((m & omask) % 16 == 0 && (m & omask) + (uint32_t)sH * gs + 16 <= (uint32_t)ysize(l) * 8u,
+                  "d=%d l=%d group %d thread %d position %d: read out of Y", d, l, g, t, pos);
+          }
       CHECK((int)F.lam.size() == (F.h + 1) * lamblock(l), "d=%d l=%d: weight block size", d, l);
     }
   std::printf(fails ? "failures: %d\n" : "ok\n", fails);
