@@ -21,8 +21,10 @@
 //   - the final weight core with the Moebius cores of the high sites
 //     precontracted into it (Sec. 4.5 applied to the high sites), in FP64:
 //     Y[S_L, s_H, j] = sum_t lambda_u(s_L + s_H, t, s_H + u - j) Z[S_L, t],
-//     u = |U_H|, the weights of the current u staged in LDS and read at
-//     wave-uniform addresses;
+//     u = |U_H|; a wave first loads the Z rows of all its tasks, then
+//     computes them; rows of one |S_L| take wave-uniform weights through
+//     scalar loads, the (row, slot) pairs of |S_L| <= 1 per-lane weights
+//     staged in LDS;
 //   - the cross-tile sum E_S += Y[S_L, |S_H|, |S_H & U_H|] in FP64 registers
 //     for the outputs of the item's group.
 // At the end of the item the FP64 partial sums go to a workspace; the
@@ -35,7 +37,8 @@
 //             phase-B states S2 overlay both (no barrier between a tile's
 //             gather and the next tile's loads)
 //   region 2: phase-A states S1 -> final states Z
-//   region 3: the final-core weights of the current |U_H|
+//   region 3: the final-core weights of the current |U_H| (per-lane reads
+//             of the |S_L| <= 1 pairs)
 //   a zero row read in place of counter rows past a unit's range
 #include <hip/hip_runtime.h>
 #include <cstdint>
@@ -267,69 +270,10 @@ struct LdsAll {
 };
 
 // ------------------------------------------------------------ weight core
-// The weights of the tile's |U_H| sit in LDS (lam), read at wave-uniform
-// addresses (broadcast).
 // Row task: 64 lanes, each owning one Z row of |S_L| = S (S >= 2) and
-// producing the slots [K0, K1) of it.
-template <int L, int S, int K0, int K1, typename SwT>
-__device__ __forceinline__ void row_task(int chunk, int lane, const SwT* Z, double* Y,
-                                         const double* lam) {
-  constexpr int NR = cbinom(B, S);
-  constexpr int RC = ZROW - S;
-  constexpr int ZB = zbase(S), LO = lamoff(L, S), YB = ybase(L, S);
-  const int row = chunk * 64 + lane;
-  const bool ok = row < NR;
-  const SwT* zr = Z + (ZB + (ok ? row : 0)) * ZROW;
-  double z[RC];
-#pragma unroll
-  for (int r = 0; r < RC; ++r) z[r] = (double)zr[r];
-  const double2* lw = reinterpret_cast<const double2*>(lam + LO);
-  double a[K1 - K0];
-#pragma unroll
-  for (int k = K0; k < K1; ++k) {
-    a[k - K0] = 0.0;
-#pragma unroll
-    for (int r = 0; r < RC; r += 2) {
-      const double2 w = lw[(k * ZROW + r) / 2];
-      a[k - K0] = fma(w.x, z[r], a[k - K0]);
-      if (r + 1 < RC) a[k - K0] = fma(w.y, z[r + 1], a[k - K0]);
-    }
-  }
-  if (ok) {
-#pragma unroll
-    for (int k = K0; k < K1; ++k) Y[YB + k * nrp(S) + row] = a[k - K0];
-  }
-}
-
-// Pair task: the (row, slot) pairs of |S_L| <= 1, 64 per task; per-lane weights.
-template <int L, typename SwT>
-__device__ __forceinline__ void pair_task(int t, int lane, const SwT* Z, double* Y,
-                                          const double* lam) {
-  constexpr int N0 = nslots(L, 0), N1 = nslots(L, 1);
-  const int p0 = t * 64 + lane;
-  const bool ok = p0 < K<L>::NPAIR;
-  const int p = ok ? p0 : 0;
-  int zrow, lofs, yidx;
-  if (p < N0) {
-    zrow = 0; lofs = K<L>::LAM0 + p * ZROW; yidx = K<L>::YB0 + p * nrp(0);
-  } else {
-    const int row = (p - N0) / N1, slot = (p - N0) - row * N1;
-    zrow = 1 + row; lofs = K<L>::LAM1 + slot * ZROW; yidx = K<L>::YB1 + slot * nrp(1) + row;
-  }
-  const SwT* zr = Z + zrow * ZROW;
-  const double2* lw = reinterpret_cast<const double2*>(lam + lofs);
-  double a = 0.0;
-#pragma unroll
-  for (int r = 0; r < ZROW; r += 2) {
-    const double2 w = lw[r / 2];
-    a = fma(w.x, (double)zr[r], a);
-    // entry 11 of an |S_L| = 1 row lies past its counters (weight 0)
-    const double z1 = (r + 1 < ZROW - 1 || zrow == 0) ? (double)zr[r + 1] : 0.0;
-    a = fma(w.y, z1, a);
-  }
-  if (ok) Y[yidx] = a;
-}
-
+// producing the slots [K0, K1) of it; the weights are the same for every
+// lane. Pair task: the (row, slot) pairs of |S_L| <= 1, 64 per task, with
+// per-lane weights.
 // Compile-time schedule of the weight-core tasks of one tile over the four
 // waves (longest task first to the least loaded wave). Row tasks of rows
 // with many slots are split into two slot ranges.
@@ -364,18 +308,127 @@ constexpr LamPlan make_lam_plan(int L) {
 }
 template <int L> struct LP { static constexpr LamPlan plan = make_lam_plan(L); };
 
-template <int L, int W, int I, typename SwT>
-__device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, const double* lam) {
-  if constexpr (I < LP<L>::plan.n) {
-    constexpr LamTask T = LP<L>::plan.t[I];
-    if constexpr (T.wave == W) {
-      if constexpr (T.kind == 0)
-        row_task<L, T.S, T.k0, T.k1, SwT>(T.chunk, lane, Z, Y, lam);
-      else
-        pair_task<L, SwT>(T.chunk, lane, Z, Y, lam);
+
+// Tasks of one wave in plan order, with the offset of each task's Z row in
+// the wave's register buffer.
+struct WaveList { int idx[40]; int n; };
+constexpr WaveList make_wave_list(int L, int W) {
+  WaveList w{};
+  w.n = 0;
+  const LamPlan p = make_lam_plan(L);
+  for (int i = 0; i < p.n; ++i)
+    if (p.t[i].wave == W) w.idx[w.n++] = i;
+  return w;
+}
+template <int L, int W> struct WL { static constexpr WaveList w = make_wave_list(L, W); };
+
+// Pass 1: every Z row (and the per-lane weights of pair tasks) of the
+// wave's tasks is loaded before any arithmetic, so the LDS latency is paid
+// once per tile.
+template <int L, int W, int J, typename SwT>
+__device__ __forceinline__ void lam_load(int lane, const SwT* Z, const double* lam,
+                                         SwT (&zb)[ZROW * (WL<L, W>::w.n > 0 ? WL<L, W>::w.n : 1)],
+                                         double (&pw)[ZROW * 2]) {
+  if constexpr (J < WL<L, W>::w.n) {
+    constexpr LamTask T = LP<L>::plan.t[WL<L, W>::w.idx[J]];
+    using V = typename Vec4<SwT>::type;
+    constexpr int VN = Vec4<SwT>::n;
+    const SwT* zr;
+    if constexpr (T.kind == 0) {
+      constexpr int NR = cbinom(B, T.S);
+      constexpr bool full = (T.chunk + 1) * 64 <= NR;
+      const int row = T.chunk * 64 + lane;
+      zr = Z + (zbase(T.S) + (full || row < NR ? row : 0)) * ZROW;
+    } else {
+      constexpr int N0 = nslots(L, 0), N1 = nslots(L, 1);
+      const int p0 = T.chunk * 64 + lane;
+      const int p = p0 < K<L>::NPAIR ? p0 : 0;
+      const bool z0 = p < N0;
+      const int row = (p - N0) / N1, slot = (p - N0) - row * N1;
+      zr = Z + (z0 ? 0 : 1 + row) * ZROW;
+      const int lofs = z0 ? K<L>::LAM0 + p * ZROW : K<L>::LAM1 + slot * ZROW;
+      const double2* lw = reinterpret_cast<const double2*>(lam + lofs);
+      constexpr int PB = (T.chunk & 1) * ZROW;   // at most two pair tasks per wave
+#pragma unroll
+      for (int q = 0; q < ZROW / 2; ++q) {
+        const double2 w = lw[q];
+        pw[PB + 2 * q] = w.x;
+        pw[PB + 2 * q + 1] = w.y;
+      }
     }
-    lam_wave<L, W, I + 1, SwT>(lane, Z, Y, lam);
+    const V* zv = reinterpret_cast<const V*>(zr);
+#pragma unroll
+    for (int q = 0; q < ZROW / VN; ++q) {
+      const V v = zv[q];
+      if constexpr (VN == 4) {
+        zb[J * ZROW + 4 * q] = v.x; zb[J * ZROW + 4 * q + 1] = v.y;
+        zb[J * ZROW + 4 * q + 2] = v.z; zb[J * ZROW + 4 * q + 3] = v.w;
+      } else {
+        zb[J * ZROW + 2 * q] = v.x; zb[J * ZROW + 2 * q + 1] = v.y;
+      }
+    }
+    lam_load<L, W, J + 1, SwT>(lane, Z, lam, zb, pw);
   }
+}
+
+// Pass 2: the slots of every task. Row tasks take their weights from the
+// constant address space (wave-uniform: scalar loads); lanes past the last
+// row write to a dump word.
+template <int L, int W, int J, typename SwT>
+__device__ __forceinline__ void lam_comp(int lane, double* Y, cdptr lamg, double* dump,
+                                         const SwT (&zb)[ZROW * (WL<L, W>::w.n > 0 ? WL<L, W>::w.n : 1)],
+                                         const double (&pw)[ZROW * 2]) {
+  if constexpr (J < WL<L, W>::w.n) {
+    constexpr LamTask T = LP<L>::plan.t[WL<L, W>::w.idx[J]];
+    if constexpr (T.kind == 0) {
+      constexpr int S = T.S, K0 = T.k0, K1 = T.k1;
+      constexpr int NR = cbinom(B, S);
+      constexpr int RC = ZROW - S;
+      constexpr int LO = lamoff(L, S), YB = ybase(L, S);
+      constexpr bool full = (T.chunk + 1) * 64 <= NR;
+      const int row = T.chunk * 64 + lane;
+      double z[RC];
+#pragma unroll
+      for (int r = 0; r < RC; ++r) z[r] = (double)zb[J * ZROW + r];
+      double a[K1 - K0];
+#pragma unroll
+      for (int k = K0; k < K1; ++k) a[k - K0] = 0.0;
+#pragma unroll
+      for (int r = 0; r < RC; ++r)
+#pragma unroll
+        for (int k = K0; k < K1; ++k) a[k - K0] = fma(lamg[LO + k * ZROW + r], z[r], a[k - K0]);
+      const bool ok = full || row < NR;
+#pragma unroll
+      for (int k = K0; k < K1; ++k) *(ok ? Y + YB + k * nrp(S) + row : dump) = a[k - K0];
+    } else {
+      constexpr int N0 = nslots(L, 0), N1 = nslots(L, 1);
+      constexpr int PB = (T.chunk & 1) * ZROW;
+      const int p0 = T.chunk * 64 + lane;
+      const bool ok = p0 < K<L>::NPAIR;
+      const int p = ok ? p0 : 0;
+      const bool z0 = p < N0;
+      const int row = (p - N0) / N1, slot = (p - N0) - row * N1;
+      const int yidx = z0 ? K<L>::YB0 + p * nrp(0) : K<L>::YB1 + slot * nrp(1) + row;
+      double a = 0.0;
+#pragma unroll
+      for (int r = 0; r < ZROW; ++r) {
+        // entry 11 of an |S_L| = 1 row lies past its counters (weight 0)
+        const double zz = (r < ZROW - 1 || z0) ? (double)zb[J * ZROW + r] : 0.0;
+        a = fma(pw[PB + r], zz, a);
+      }
+      *(ok ? Y + yidx : dump) = a;
+    }
+    lam_comp<L, W, J + 1, SwT>(lane, Y, lamg, dump, zb, pw);
+  }
+}
+
+template <int L, int W, typename SwT>
+__device__ __forceinline__ void lam_wave(int lane, const SwT* Z, double* Y, const double* lam,
+                                         cdptr lamg, double* dump) {
+  SwT zb[ZROW * (WL<L, W>::w.n > 0 ? WL<L, W>::w.n : 1)];
+  double pw[ZROW * 2];
+  lam_load<L, W, 0, SwT>(lane, Z, lam, zb, pw);
+  lam_comp<L, W, 0, SwT>(lane, Y, lamg, dump, zb, pw);
 }
 
 // Phase B of one wave: every sigma_A of the wave has SAMIN <= |sigma_A| <=
@@ -727,11 +780,17 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     }
     __syncthreads();
     // ---- final weight core -> Y ----
-    switch (wave) {
-      case 0: lam_wave<L, 0, 0, SwT>(lane, Z, Y, lamL); break;
-      case 1: lam_wave<L, 1, 0, SwT>(lane, Z, Y, lamL); break;
-      case 2: lam_wave<L, 2, 0, SwT>(lane, Z, Y, lamL); break;
-      default: lam_wave<L, 3, 0, SwT>(lane, Z, Y, lamL); break;
+    {
+      const cdptr lamg = (cdptr)(C->lam + (int64_t)u_prev * LB);
+      // lanes past a task's rows write here: the transpose region, dead
+      // between phase C and the next tile
+      double* dump = reinterpret_cast<double*>(smem);
+      switch (wave) {
+        case 0: lam_wave<L, 0, SwT>(lane, Z, Y, lamL, lamg, dump); break;
+        case 1: lam_wave<L, 1, SwT>(lane, Z, Y, lamL, lamg, dump); break;
+        case 2: lam_wave<L, 2, SwT>(lane, Z, Y, lamL, lamg, dump); break;
+        default: lam_wave<L, 3, SwT>(lane, Z, Y, lamL, lamg, dump); break;
+      }
     }
     __syncthreads();
     // ---- cross-tile sum: E_S += Y[S_L, s_H, |S_H & U_H|] ----
