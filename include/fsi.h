@@ -153,11 +153,12 @@ typedef struct {
 
 /* Tile kernel of the fused algorithm. The register-phase kernel (tiles of
  * 11 low bits) covers every storage dtype and precision except
- * F32_FP64REG, at l <= 3 for 11 <= d <= 30 and at l = 4 for 11 <= d <= 29
- * (the high bits its output metadata holds bound the rest; past d = 20 at
- * l = 4 the outputs are split into groups, each gathered by its own pass
- * over the tiles); the generic LDS kernel covers every (d, l). AUTO picks
- * the register-phase kernel where it applies. */
+ * F32_FP64REG, at l <= 4 for 11 <= d <= 30 (past d = 20 at l = 4 the outputs
+ * outnumber a workgroup's accumulators: a work item then covers a block of
+ * 2^6 tiles sharing their top high bits, and the wide gather combines the
+ * blocks' partial sums; every tile is still read and swept once); the
+ * generic LDS kernel covers every (d, l). AUTO picks the register-phase
+ * kernel where it applies. */
 typedef enum {
   FSI_KERNEL_AUTO = 0,
   FSI_KERNEL_GENERIC = 1,
@@ -176,8 +177,14 @@ typedef struct fsi_batch_plan_s* fsi_batch_plan_t;
  * tiles per work item and the generic kernel at the largest tile that fits
  * LDS and 1 or 2 bits less; for the two-pass algorithm 4, 5 or 6 bits per
  * strided high Moebius pass, with the largest tile or 1 bit less. The
- * choice is cached per (dtype, precision, algo, kernel, tile_bits, multiset
- * of (d, l)) for the life of the process. */
+ * choice is cached per (device architecture and compute-unit count, dtype,
+ * precision, algo, kernel, tile_bits, input, multiset of (d, l)) in the
+ * process and in a JSON file read by later processes: the path in the
+ * environment variable FSI_TUNE_CACHE (empty: no file), by default
+ * $HOME/.cache/fsi_mi355x/autotune.json. A plan whose schedule comes from
+ * the cache reports autotuned = 1 and tuned_ms = 0. The file only saves
+ * plan time: when it is missing, unreadable or unwritable, plans are timed
+ * as without it. */
 typedef struct {
   int32_t autotuned;        /* 1 if chosen by timing                         */
   int32_t fast_instances;   /* instances on the register-phase kernel       */

@@ -9,6 +9,8 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <utility>
 #include <vector>
 
@@ -103,6 +105,7 @@ struct fsi_batch_plan_s {
   // workspace): the no-allocation entry point carves them from its static
   // scratch array instead
   size_t partial_bytes = 0, y_bytes = 0, wide_bytes = 0, work_bytes = 0;
+  int64_t ylo_off = -1;            // two-pass FP64: low words at Y + ylo_off
   // recorded after every apply on the caller's stream (outside stream
   // capture): destroying the plan waits for it, not for the whole device
   hipEvent_t done = nullptr;
@@ -249,14 +252,17 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     auto it = cls_index.find(key);
     if (it == cls_index.end()) {
       ClassHost C;
-      // register-phase kernel: fused algorithm, l <= 4, tile of 11 bits,
-      // at most 12 high bits, at most 25 outputs per thread
+      // register-phase kernel: fused algorithm, l <= 4, tile of 11 bits. An
+      // instance with d < 11 runs as the d = 11 instance of the game that
+      // ignores the players past d: its Moebius coefficients vanish on every
+      // set holding one of them and the weights W(s, t) do not depend on d,
+      // so the outputs of the sets inside [d] are the instance's own
       const int fb = kFastTileBits;
       const int kern = sc.kernel >= 0 ? sc.kernel : opts.kernel;
+      const int dfast = std::max(dh[i], fb);
       const bool want_fast = kern != FSI_KERNEL_GENERIC && algo == ALGO_FUSED &&
-                             fast_supported(prec) && lh[i] <= kFastMaxL && dh[i] >= fb &&
-                             dh[i] - fb <= fast_max_high_bits(lh[i]) &&
-                             fast_output_slots(dh[i], lh[i]) >= 0 &&
+                             fast_supported(prec) && lh[i] <= kFastMaxL &&
+                             fast_block_bits(dfast, lh[i]) >= 0 &&
                              (opts.tile_bits == 0 || opts.tile_bits == fb);
       if (kern == FSI_KERNEL_REGISTER && !want_fast) {
         return fail(FSI_ERR_UNSUPPORTED, "register-phase kernel does not apply to instance " +
@@ -264,8 +270,14 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       }
       int b = want_fast ? fb : choose_tile_bits(dh[i], lh[i], prec, opts.tile_bits);
       if (!want_fast && opts.tile_bits == 0) b = std::max(1, b + sc.tb_shift);
-      std::string err = build_class(dh[i], lh[i], b, algo, opts.index, opts.input, &C);
+      std::string err = build_class(want_fast ? dfast : dh[i], lh[i], b, algo, opts.index,
+                                    opts.input, &C);
       if (!err.empty()) { return fail(FSI_ERR_INTERNAL, err); }
+      if (want_fast && dh[i] < fb) {
+        // the outputs are those of the instance's own d
+        C.out_masks = canonical_masks(dh[i], lh[i]);
+        C.M = (int)C.out_masks.size();
+      }
       const int64_t need = std::max<int64_t>(2 * (int64_t)C.lds_elems * (int64_t)sweep_elem_bytes(prec),
                                              ((int64_t)1 << b) * (int64_t)mob_elem_bytes(prec));
       if (!want_fast && need > kLdsBudget) {
@@ -304,30 +316,33 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     insts[i].ooff = P->ooff[i];
     insts[i].yoff = ytot;
     insts[i].woff = single ? 0 : wtot;
-    ytot += ((int64_t)1 << C.h) * C.Ysize;
+    // per-tile results in HBM only for the generic kernel (the register-phase
+    // kernel keeps them in LDS)
+    if (P->fast_of[P->cls_of[i]] < 0) ytot += ((int64_t)1 << C.h) * C.Ysize;
     wtot += (int64_t)1 << dh[i];
   }
   // register-phase work items: runs of tiles of one instance, in the order of
-  // the class's tile list (high indices sorted by popcount, so the final
-  // weights change at most h + 1 times per instance)
+  // the class's tile list: block by block (blocks of 2^kb tiles sharing
+  // their top h - kb high bits; one block when kb = h), the tiles of a block
+  // sorted by popcount, so the final weights change at most kb + 1 times
+  // per block
   std::vector<int32_t> torder;
   std::vector<int32_t> tofs_of_fast(P->fclasses.size(), 0);
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     tofs_of_fast[f] = (int32_t)torder.size();
-    const int h = P->fclasses[f].h;
-    std::vector<int32_t> ord((size_t)1 << h);
+    const int h = P->fclasses[f].h, kb = P->fclasses[f].kb;
+    std::vector<int32_t> ord((size_t)1 << kb);
     for (size_t t = 0; t < ord.size(); ++t) ord[t] = (int32_t)t;
     std::stable_sort(ord.begin(), ord.end(), [](int32_t x, int32_t y) {
       return __builtin_popcount(x) < __builtin_popcount(y);
     });
-    torder.insert(torder.end(), ord.begin(), ord.end());
+    for (int64_t blk = 0; blk < ((int64_t)1 << (h - kb)); ++blk)
+      for (int32_t t : ord) torder.push_back((int32_t)((blk << kb) | t));
   }
-  // tiles the register-phase kernel walks (each output group walks them all)
+  // tiles the register-phase kernel walks
   int64_t fast_tiles = 0;
-  for (int i = 0; i < n; ++i) {
-    const int f = P->fast_of[P->cls_of[i]];
-    if (f >= 0) fast_tiles += ((int64_t)1 << P->classes[P->cls_of[i]].h) * P->fclasses[f].ngroups;
-  }
+  for (int i = 0; i < n; ++i)
+    if (P->fast_of[P->cls_of[i]] >= 0) fast_tiles += (int64_t)1 << P->classes[P->cls_of[i]].h;
   // tiles per work item: the largest power of two that still gives every
   // workgroup slot of the machine at least one item
   int64_t chunk = 1;
@@ -339,49 +354,37 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     if (sc.chunk_shift > 0) chunk <<= sc.chunk_shift;
     if (sc.chunk_shift < 0) chunk = std::max<int64_t>(1, chunk >> -sc.chunk_shift);
   }
-  // work items: output group major, then tile ranges; the partial sums of
-  // item (g, r) of an instance start at pbase + (g * nitems + r) * pstride
+  // work items: tile ranges of 2^c tiles inside a block (c <= kb), block
+  // by block; item j of an instance covers block j / ipb and has its partial
+  // sums at pbase + j * pstride
   std::vector<FastItem> fitems;
   int64_t ptot = 0;
   for (int i = 0; i < n; ++i) {
     const int f = P->fast_of[P->cls_of[i]];
     if (f < 0) continue;
     const FastClassHost& F = P->fclasses[f];
-    const int64_t ntile = (int64_t)1 << F.h;
-    const int64_t cs = std::min<int64_t>(chunk, ntile);
+    const int64_t ntile = (int64_t)1 << F.h, bsize = (int64_t)1 << F.kb;
+    const int64_t cs = std::min<int64_t>(chunk, bsize);
     insts[i].fast = 1;
     insts[i].fcls = f;
     insts[i].tofs = tofs_of_fast[f];
     insts[i].pbase = ptot;
     insts[i].pstride = F.nkk * kFastThreads;
-    insts[i].nitems = (int32_t)((ntile + cs - 1) / cs);
-    for (int g = 0; g < F.ngroups; ++g)
-      for (int64_t tb = 0; tb < ntile; tb += cs) {
-        fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min(ntile, tb + cs), g, ptot});
-        ptot += (int64_t)F.nkk * kFastThreads;
-      }
-  }
-  // per class: position of each canonical output in an instance's partial
-  // sums (its group's first item plus its slot)
-  std::vector<std::vector<int32_t>> fpidx(P->fclasses.size());
-  for (size_t f = 0; f < P->fclasses.size(); ++f) {
-    const FastClassHost& F = P->fclasses[f];
-    const int64_t ntile = (int64_t)1 << F.h;
-    const int64_t cs = std::min<int64_t>(chunk, ntile);
-    const int64_t nr = (ntile + cs - 1) / cs;
-    const int64_t pstride = (int64_t)F.nkk * kFastThreads;
-    fpidx[f].resize(F.pidx.size());
-    for (size_t k = 0; k < F.pidx.size(); ++k) {
-      const int64_t pos = (int64_t)F.pgroup[k] * nr * pstride + F.pidx[k];
-      if (pos >= ((int64_t)1 << 31)) { return fail(FSI_ERR_INTERNAL, "partial sums too large"); }
-      fpidx[f][k] = (int32_t)pos;
+    insts[i].nitems = (int32_t)(ntile / cs);
+    insts[i].ipb = (int32_t)(bsize / cs);
+    insts[i].pw = F.l + 1;
+    insts[i].lowmask = dh[i] < kFastTileBits ? (1 << dh[i]) - 1 : (1 << kFastTileBits) - 1;
+    for (int64_t tb = 0; tb < ntile; tb += cs) {
+      fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)(tb + cs), 0, ptot});
+      ptot += (int64_t)F.nkk * kFastThreads;
     }
   }
-  // reduction of the register-phase partial sums: one output per thread when
-  // no instance has more than two items per output, else four item rows
+  // reduction of the register-phase partial sums of one-block instances: one
+  // output per thread when no instance has more than two items per output,
+  // else four item rows; instances of several blocks go to the wide gather
   int red_rows = 1;
   for (int i = 0; i < n; ++i)
-    if (insts[i].fast && insts[i].nitems > 2) red_rows = 4;
+    if (insts[i].fast && insts[i].nitems > 2 && insts[i].nitems == insts[i].ipb) red_rows = 4;
   const int red_width = kFastThreads / red_rows;
   std::vector<int2> red_chunks;
   int n_generic = 0;
@@ -392,11 +395,16 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       if (!insts[i].wide) ++n_generic;
       continue;
     }
+    if (insts[i].nitems > insts[i].ipb) {
+      insts[i].wide = 1;
+      continue;
+    }
     const int Mi = P->classes[P->cls_of[i]].M;
     for (int k0 = 0; k0 < Mi; k0 += red_width) red_chunks.push_back(make_int2(i, k0));
   }
-  // wide gather items: per instance, output groups x tile ranges; the ranges
-  // (a power of two) give the machine about two items per CU
+  // wide gather items: per instance, output groups x ranges of tiles
+  // (generic instances) or blocks (register-phase instances); the ranges (a
+  // power of two) give the machine about two items per CU
   std::vector<WideItem> witems;
   std::vector<WideGroup> wgroups;
   int64_t wptot = 0;
@@ -409,7 +417,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     for (int i = 0; i < n; ++i) {
       if (!insts[i].wide) continue;
       const ClassHost& C = P->classes[P->cls_of[i]];
-      const int64_t ntile = (int64_t)1 << C.h;
+      const int64_t ntile =
+          insts[i].fast ? (int64_t)insts[i].nitems / insts[i].ipb : (int64_t)1 << C.h;
       const int64_t nr = std::min(nr_target, ntile);
       const int64_t per = ntile / nr;
       const int G = (C.M + kWideOuts - 1) / kWideOuts;
@@ -485,7 +494,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   // ---- device arena ----
   std::vector<unsigned char> buf;
   std::vector<ClassDev> cdev(P->classes.size());
-  struct Offs { size_t step_off, step_np, pat, ytab, lam, lam_soff, oinfo, osh; };
+  struct Offs { size_t step_off, step_np, pat, ytab, lam, lam_lo, lam_soff, oinfo, osh; };
   std::vector<Offs> co(P->classes.size());
   for (size_t c = 0; c < P->classes.size(); ++c) {
     const ClassHost& C = P->classes[c];
@@ -494,20 +503,21 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].pat = stage(buf, C.pat.data(), C.pat.size());
     co[c].ytab = stage(buf, C.ytab.data(), C.ytab.size());
     co[c].lam = stage(buf, C.lam.data(), C.lam.size());
+    co[c].lam_lo = stage(buf, C.lam_lo.data(), C.lam_lo.size());
     co[c].lam_soff = stage(buf, C.lam_soff.data(), C.lam_soff.size());
     co[c].oinfo = stage(buf, C.oinfo.data(), C.oinfo.size());
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
   std::vector<FastClassDev> fdev(P->fclasses.size());
-  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm, gnkk; };
+  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm, osh2; };
   std::vector<FOffs> fo(P->fclasses.size());
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     fo[f].lam = stage(buf, F.lam.data(), F.lam.size());
     fo[f].meta = stage(buf, F.meta.data(), F.meta.size());
     fo[f].gs8 = stage(buf, F.gs8.data(), F.gs8.size());
-    fo[f].pidx = stage(buf, fpidx[f].data(), fpidx[f].size());
-    fo[f].gnkk = stage(buf, F.gnkk.data(), F.gnkk.size());
+    fo[f].pidx = stage(buf, F.pidx.data(), F.pidx.size());
+    fo[f].osh2 = stage(buf, F.osh2.data(), F.osh2.size());
     fo[f].unit_mask = stage(buf, F.unit_mask.data(), F.unit_mask.size());
     fo[f].zrow = stage(buf, F.zrow.data(), F.zrow.size());
     fo[f].uperm = stage(buf, F.uperm.data(), F.uperm.size());
@@ -540,6 +550,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.pat = reinterpret_cast<const uint32_t*>(A + co[c].pat);
     D.ytab = reinterpret_cast<const uint32_t*>(A + co[c].ytab);
     D.lam = reinterpret_cast<const double*>(A + co[c].lam);
+    D.lam_lo = C.lam_lo.empty() ? nullptr : reinterpret_cast<const double*>(A + co[c].lam_lo);
     D.lam_soff = reinterpret_cast<const int32_t*>(A + co[c].lam_soff);
     D.oinfo = reinterpret_cast<const uint32_t*>(A + co[c].oinfo);
     D.osh = reinterpret_cast<const uint32_t*>(A + co[c].osh);
@@ -550,7 +561,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
     FastClassDev& D = fdev[f];
-    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk; D.mshift = F.mshift;
+    D.d = F.d; D.l = F.l; D.h = F.h; D.M = F.M; D.nkk = F.nkk; D.mshift = F.mshift; D.kb = F.kb;
     fast_lds[F.l] = fast_lds_bytes(prec, F.l);
     fast_lds_max = std::max(fast_lds_max, fast_lds[F.l]);
     D.lam = reinterpret_cast<const double*>(A + fo[f].lam);
@@ -559,20 +570,27 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     D.unit_mask = reinterpret_cast<const int32_t*>(A + fo[f].unit_mask);
     D.zrow = reinterpret_cast<const int32_t*>(A + fo[f].zrow);
     D.uperm = reinterpret_cast<const int32_t*>(A + fo[f].uperm);
-    D.gnkk = reinterpret_cast<const int32_t*>(A + fo[f].gnkk);
   }
   if (fast_lds_max > 160 * 1024) {
     return fail(FSI_ERR_INTERNAL, "register-phase kernel does not fit in LDS");
   }
   std::memcpy(buf.data() + o_fcls, fdev.data(), fdev.size() * sizeof(FastClassDev));
   for (int i = 0; i < n; ++i)
-    if (insts[i].fast) insts[i].pidx = reinterpret_cast<const int32_t*>(A + fo[insts[i].fcls].pidx);
+    if (insts[i].fast) {
+      insts[i].pidx = reinterpret_cast<const int32_t*>(A + fo[insts[i].fcls].pidx);
+      insts[i].osh2 = reinterpret_cast<const uint32_t*>(A + fo[insts[i].fcls].osh2);
+    }
   // instance descriptors carry the fast fields filled above
   std::memcpy(buf.data() + o_inst, insts.data(), insts.size() * sizeof(InstDev));
   e = hipMemcpy(P->arena, buf.data(), buf.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) { return fail(FSI_ERR_HIP, "hipMemcpy(tables) failed"); }
 
-  e = hipMalloc(reinterpret_cast<void**>(&P->Y), std::max<int64_t>(ytot, 1) * sizeof(double));
+  // the two-pass FP64 path keeps each per-tile result as a double-double
+  // (high words, then low words)
+  const bool ycomp = algo == ALGO_TWO_PASS && prec == PREC_F64;
+  const int64_t ywords = std::max<int64_t>(ytot, 1) * (ycomp ? 2 : 1);
+  P->ylo_off = ycomp ? std::max<int64_t>(ytot, 1) : -1;
+  e = hipMalloc(reinterpret_cast<void**>(&P->Y), ywords * sizeof(double));
   if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(Y) failed"); }
   if (algo == ALGO_TWO_PASS && !P->in_place) {
     const size_t wbytes = (size_t)wtot *
@@ -622,6 +640,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   a.out_offset = reinterpret_cast<const int64_t*>(A + o_ooff);
   a.total_out = P->ooff[n];
   a.Y = P->Y;
+  a.Ylo = P->ylo_off >= 0 ? P->Y + P->ylo_off : nullptr;
   a.work = P->work;
   a.grid_tile = std::max(1, std::min<int>((int)std::max(tiles.size(), all_tiles.size()), n_cu * per_cu));
   a.grid_reduce = (int)std::max<int64_t>(1, std::min<int64_t>((a.total_out + 255) / 256, (int64_t)n_cu * 8));
@@ -652,12 +671,9 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     a.fast.torder = reinterpret_cast<const int32_t*>(A + o_torder);
     a.fast.partial = P->partial;
     for (int l = 0; l <= kFastMaxL + 1; ++l) a.fast.lbeg[l] = lbeg[l];
-    for (int l = 0; l <= kFastMaxL; ++l) a.fast.grouped[l] = 0;
     a.fast.mobius_in = 0;
-    for (const FastClassHost& F : P->fclasses) {
-      if (F.ngroups > 1) a.fast.grouped[F.l] = 1;
+    for (const FastClassHost& F : P->fclasses)
       if (F.mobius_in) a.fast.mobius_in = 1;
-    }
     int wgs = 1;
     a.fast.lds_mixed = 0;
     for (int l = 0; l <= kFastMaxL; ++l) {
@@ -679,7 +695,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   P->sched.mob_group = algo == ALGO_TWO_PASS ? (sc.mob_group > 0 ? sc.mob_group : 6) : 0;
   P->sched.tuned_ms = 0.f;
   P->partial_bytes = (size_t)ptot * sizeof(double);
-  P->y_bytes = (size_t)std::max<int64_t>(ytot, 1) * sizeof(double);
+  P->y_bytes = (size_t)ywords * sizeof(double);
   P->wide_bytes = (size_t)wptot * sizeof(double);
   P->work_bytes = (algo == ALGO_TWO_PASS && !P->in_place)
                       ? (size_t)wtot * std::max(mob_elem_bytes(prec), (size_t)8)
@@ -695,12 +711,74 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
 // With fsi_plan_opts.autotune = 1 the plan is built for each candidate
 // schedule, each candidate is timed on zero-filled device buffers of the
 // plan's size (the kernels' work does not depend on the values), and the
-// fastest is kept. Results are cached per (dtype, precision, algo, kernel,
-// tile_bits, multiset of (d, l)) for the life of the process.
+// fastest is kept. Results are cached per (device architecture and compute
+// units, dtype, precision, algo, kernel, tile_bits, input, multiset of
+// (d, l)): in the process, and in a JSON file that later processes read
+// (the path in FSI_TUNE_CACHE, an empty value for none; by default
+// $HOME/.cache/fsi_mi355x/autotune.json). The file is an optimisation
+// only: a missing, unreadable or unwritable file changes nothing else.
 std::mutex g_tune_mu;
 std::map<std::string, Sched>& tune_cache() {
   static std::map<std::string, Sched> m;
   return m;
+}
+
+std::string tune_file_path() {
+  const char* env = std::getenv("FSI_TUNE_CACHE");
+  if (env) return std::string(env);
+  const char* home = std::getenv("HOME");
+  if (!home || !*home) return "";
+  return std::string(home) + "/.cache/fsi_mi355x/autotune.json";
+}
+
+// One entry per line:
+//   {"key": "...", "kernel": K, "tb_shift": T, "chunk_shift": C, "mob_group": G},
+// inside {"format": "fsi-autotune-1", "entries": [ ... ]}. Keys hold only
+// [0-9a-z/;,x-], so no escapes are needed; lines that do not parse are
+// skipped.
+void tune_file_load(std::map<std::string, Sched>& m) {
+  const std::string path = tune_file_path();
+  if (path.empty()) return;
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[4096];
+  while (std::fgets(line, sizeof line, f)) {
+    const char* k = std::strstr(line, "\"key\": \"");
+    if (!k) continue;
+    k += 8;
+    const char* ke = std::strchr(k, '"');
+    if (!ke) continue;
+    Sched sc;
+    if (std::sscanf(ke + 1, ", \"kernel\": %d, \"tb_shift\": %d, \"chunk_shift\": %d, \"mob_group\": %d",
+                    &sc.kernel, &sc.tb_shift, &sc.chunk_shift, &sc.mob_group) != 4)
+      continue;
+    m.emplace(std::string(k, ke), sc);
+  }
+  std::fclose(f);
+}
+
+void tune_file_save(const std::map<std::string, Sched>& m) {
+  const std::string path = tune_file_path();
+  if (path.empty()) return;
+  // create the default directory (two levels below $HOME) if needed
+  for (size_t p = path.find('/', 1); p != std::string::npos; p = path.find('/', p + 1))
+    (void)mkdir(path.substr(0, p).c_str(), 0755);
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  bool ok = std::fprintf(f, "{\"format\": \"fsi-autotune-1\", \"entries\": [\n") > 0;
+  size_t i = 0;
+  for (const auto& e : m) {
+    ok = ok && std::fprintf(f,
+                            "{\"key\": \"%s\", \"kernel\": %d, \"tb_shift\": %d, "
+                            "\"chunk_shift\": %d, \"mob_group\": %d}%s\n",
+                            e.first.c_str(), e.second.kernel, e.second.tb_shift,
+                            e.second.chunk_shift, e.second.mob_group,
+                            ++i < m.size() ? "," : "") > 0;
+  }
+  ok = ok && std::fprintf(f, "]}\n") > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
 }
 
 std::string tune_key(int n, const int* dh, const int* lh, const fsi_plan_opts& o) {
@@ -753,9 +831,21 @@ fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts*
   if (opts_in) opts = *opts_in;
   if (!opts.autotune) return build_batch(n, dh, lh, opts_in, single, out);
   if (n < 1 || !dh || !lh) return build_batch(n, dh, lh, opts_in, single, out);
-  const std::string key = tune_key(n, dh, lh, opts);
+  std::string key = tune_key(n, dh, lh, opts);
+  {
+    int dev = 0, ncu = 0;
+    std::string why;
+    // without a gfx950 device the plain build reports why
+    if (!device_is_gfx950(&dev, &ncu, &why)) return build_batch(n, dh, lh, opts_in, single, out);
+    key = "gfx950-" + std::to_string(ncu) + "cu/" + key;
+  }
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    static bool loaded = false;
+    if (!loaded) {
+      loaded = true;
+      tune_file_load(tune_cache());
+    }
     auto it = tune_cache().find(key);
     if (it != tune_cache().end()) {
       fsi_status st = build_batch(n, dh, lh, opts_in, single, out, it->second);
@@ -824,6 +914,7 @@ fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts*
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache()[key] = best_s;
+    tune_file_save(tune_cache());
   }
   best->sched.autotuned = 1;
   best->sched.tuned_ms = best_ms;
@@ -1045,6 +1136,7 @@ fsi_status fsi_apply_batched_noalloc(fsi_batch_plan_t plan, const void* values_d
   a.fast.partial = part;
   off += align256(plan->partial_bytes);
   a.Y = reinterpret_cast<double*>(base + off);
+  a.Ylo = plan->ylo_off >= 0 ? a.Y + plan->ylo_off : nullptr;
   off += align256(plan->y_bytes);
   a.wide_partial = plan->wide_bytes ? reinterpret_cast<double*>(base + off) : nullptr;
   off += align256(plan->wide_bytes);

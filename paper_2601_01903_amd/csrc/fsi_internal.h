@@ -31,6 +31,7 @@ struct ClassDev {
   const uint32_t* pat;      // (src0+1) | (src1+1) << 16 per output pattern
   const uint32_t* ytab;     // [Ysize] final-pattern base | slot << 16 | s_L << 26
   const double* lam;        // [(h+1) * lam_ublock]
+  const double* lam_lo;     // two-pass: [(h+1) * lam_ublock] low words of the weights, else null
   const int32_t* lam_soff;  // [l+1] offset of the s_L block inside a u block
   const uint32_t* oinfo;    // [M] Y offset of S_L | s_H << 24
   const uint32_t* osh;      // [M] S_H (mask over the h high bits)
@@ -40,32 +41,36 @@ struct ClassDev {
 // low bits, l <= 4. The in-tile layouts are compile-time functions of l; the
 // tables here hold what depends on d (weights, output metadata) and the
 // per-thread unit maps of the sweep phases.
-// Outputs are held by the kernel in slots: thread t owns the outputs
-// (kk, t), kk = 0 .. nkk-1; slot kk holds outputs of one |S_L| only, so the
-// stride between the j-variants of its partial results is uniform.
+// Partial sums are held by the kernel in slots: thread t owns the slots
+// (kk, t), kk = 0 .. nkk-1; slot kk holds sums of one |S_L| only, so the
+// stride between the j-variants of its per-tile results is uniform. An
+// instance whose outputs all fit the slots is one block (kb = h: a slot sums
+// an output); otherwise a work item covers a block of 2^kb tiles and its
+// slots hold the block's partial sums over (S_L, S_H1, s_H2, j2), from which
+// the reduction picks j2 = |S_H2 & block| per output.
 struct FastClassDev {
   int32_t d, l, h, M;
-  int32_t nkk;                // slots per thread in use (largest over the output groups)
+  int32_t nkk;                // slots per thread in use
   int32_t mshift;             // bits of the Y byte offset in a metadata word
-  int32_t pad0, pad1;
+  int32_t kb, pad1;           // low high bits per block (h: the whole instance)
   const double* lam;          // [(h+1) * lamblock(l)] final-core weights per high popcount
-  const uint32_t* meta;       // [groups * 256 * kFastMetaStride] per group and thread:
-                              // Y byte offset | S_H << mshift
-  const uint32_t* gs8;        // [groups * kFastMetaStride] byte stride between j-variants per slot
-  const int32_t* gnkk;        // [groups] slots per thread in use in each output group
+  const uint32_t* meta;       // [256 * kFastMetaStride] per thread and position:
+                              // Y byte offset | S_H (blocked: S_H1) << mshift
+  const uint32_t* gs8;        // [kFastRuns * 4] byte stride between j-variants per position and wave
   const int32_t* unit_mask;   // [n3(l)] sigma_A | sigma_B << 4 of a phase-C unit
   const int32_t* zrow;        // [n3(l) * 8] Z row of (unit, sigma_C)
   const int32_t* uperm;       // [256] phase-C unit of thread t, -1 for none (heavy units on two lanes)
 };
 
 struct FastClassHost {
-  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16, ngroups = 1, mobius_in = 0;
+  int d = 0, l = 0, h = 0, M = 0, nkk = 0, mshift = 16, kb = 0, mobius_in = 0;
   std::vector<double> lam;
   std::vector<uint32_t> meta, gs8;
-  std::vector<int32_t> gnkk;
   std::vector<int32_t> unit_mask, zrow, uperm;
-  std::vector<int32_t> pidx;    // [M] slot index kk * 256 + t of canonical output k in its group
-  std::vector<int32_t> pgroup;  // [M] output group of canonical output k
+  // [M * (l + 1)] slot index kk * 256 + t of canonical output k's partial
+  // sum for j2 = 0 .. l (whole instances: every entry the j2 = 0 slot)
+  std::vector<int32_t> pidx;
+  std::vector<uint32_t> osh2;   // [M] S_H2 = S_H >> kb of canonical output k
 };
 
 struct InstDev {
@@ -81,8 +86,15 @@ struct InstDev {
   int32_t fcls;      // index into the register-phase class array
   int64_t pbase;     // first partial sum (doubles)
   int32_t pstride;   // partial sums per work item
-  int32_t wide;      // 1: generic instance reduced by the wide gather
-  const int32_t* pidx;  // [M] position of canonical output k in an item's partial sums
+  int32_t wide;      // 1: reduced by the wide gather (generic instances with
+                     // many tiles, register-phase instances of several blocks)
+  int32_t pw;        // row width of pidx (l + 1)
+  int32_t ipb;       // work items per block (item j covers block j / ipb)
+  int32_t lowmask;   // register-phase kernel: 2^d - 1 for d < 11 (the tile's
+                     // value U is v(U & lowmask)), else 2^11 - 1
+  int32_t pad2;
+  const int32_t* pidx;   // [M * pw] position of canonical output k's partial sum for j2
+  const uint32_t* osh2;  // [M] S_H2 of canonical output k
 };
 
 // Host-side tables of one class (built once, uploaded into a device arena).
@@ -91,7 +103,7 @@ struct ClassHost {
   int M = 0, Ysize = 0, lam_ublock = 0, lds_elems = 0, nfinal = 0;
   std::vector<int32_t> step_off, step_np;
   std::vector<uint32_t> pat, ytab, oinfo, osh, out_masks;
-  std::vector<double> lam;
+  std::vector<double> lam, lam_lo;
   std::vector<int32_t> lam_soff;
 };
 
@@ -108,10 +120,12 @@ double weight_full(int s, int t, int l, int index);
 int64_t sweep_peak_entries(int b, int l);
 // Builds all tables for one class; returns "" or an error message.
 std::string build_class(int d, int l, int b, int algo, int index, int mobius_in, ClassHost* out);
-// Output slots per thread the register-phase kernel needs for (d, l), or -1.
+// Low high bits per block of the register-phase kernel for (d, l): h = d - 11
+// when every output fits the workgroup's slots, else the most that fit; -1
+// when the kernel does not apply.
+int fast_block_bits(int d, int l);
+// Slots per thread the register-phase kernel uses for (d, l), or -1.
 int fast_output_slots(int d, int l);
-// Most high bits (d - 11) the register-phase kernel's output metadata holds at order l.
-int fast_max_high_bits(int l);
 // Builds the register-phase kernel tables from an already built fused class
 // with b = 11 and l <= 4 (its final weights and output order).
 std::string build_fast_class(const ClassHost& C, FastClassHost* out);

@@ -28,7 +28,7 @@ constexpr int kFastTileBits = 11;
 constexpr int kFastMaxL = 4;
 
 struct FastItem {
-  int32_t inst, tb, te, group;     // tiles [tb, te) of the instance's tile order; output group
+  int32_t inst, tb, te, pad;       // tiles [tb, te) of the instance's tile order
   int64_t pofs;                    // partial sums of this item
 };
 
@@ -43,7 +43,6 @@ struct FastLaunch {
   int lbeg[kFastMaxL + 2];
   int grid[kFastMaxL + 1];
   size_t lds[kFastMaxL + 1];
-  int grouped[kFastMaxL + 1];     // 1: an instance of this order has several output groups
   int grid_mixed;                 // grid of the one launch over every order's items
   size_t lds_mixed;               // its dynamic LDS (the largest order's)
   int mobius_in;                  // 1: the input is already the Moebius transform
@@ -103,6 +102,7 @@ struct LaunchArgs {
   void* out;
   void* work;                 // Moebius workspace (two-pass, fsi_mobius)
   double* Y;
+  double* Ylo;                // two-pass FP64: low words of the per-tile results (else null)
   int grid_tile, grid_reduce;
   size_t tile_lds, mob_lds;
   const double* partial;      // register-phase kernel partial sums

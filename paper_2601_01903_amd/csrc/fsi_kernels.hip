@@ -80,7 +80,7 @@ template <typename SrcT, typename MobT, typename SwT, bool kMobius>
 __global__ void __launch_bounds__(kTileThreads)
 tile_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
             const TileItem* __restrict__ items, int n_items, const SrcT* __restrict__ src,
-            double* __restrict__ Y) {
+            double* __restrict__ Y, double* __restrict__ Ylo) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int tid = threadIdx.x;
   constexpr int NT = kTileThreads;
@@ -167,9 +167,33 @@ tile_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ in
       const int slot = (int)((q >> 16) & 0x3FFu);
       const int sl = (int)(q >> 26);
       const double* lw = lamu + C->lam_soff[sl] + slot * (b + 1);
-      double acc = 0.0;
-      for (int t = sl; t <= b; ++t) acc = fma(lw[t], (double)cur[fp + t - sl], acc);
-      Yt[e] = acc;
+      if (Ylo) {
+        // compensated dot product with double-double weights (the
+        // error-free product of the high word by FMA and Knuth's TwoSum,
+        // their errors and the low word's product summed apart): the result
+        // as a double-double; no contraction, so every sum and product is
+        // rounded as written
+#pragma clang fp contract(off)
+        const double* lwlo = C->lam_lo + (int64_t)u * C->lam_ublock + C->lam_soff[sl] + slot * (b + 1);
+        double s = 0.0, c = 0.0;
+        for (int t = sl; t <= b; ++t) {
+          const double z = (double)cur[fp + t - sl];
+          const double p = lw[t] * z;
+          const double pe = fma(lw[t], z, -p);
+          const double s1 = s + p;
+          const double bb = s1 - s;
+          c += ((s - (s1 - bb)) + (p - bb)) + (pe + lwlo[t] * z);
+          s = s1;
+        }
+        const double hi = s + c;
+        const double bb = hi - s;
+        Yt[e] = hi;
+        Ylo[I.yoff + (int64_t)w.tile * C->Ysize + e] = (s - (hi - bb)) + (c - bb);
+      } else {
+        double acc = 0.0;
+        for (int t = sl; t <= b; ++t) acc = fma(lw[t], (double)cur[fp + t - sl], acc);
+        Yt[e] = acc;
+      }
     }
     __syncthreads();
   }
@@ -180,8 +204,8 @@ template <typename OutT>
 __global__ void __launch_bounds__(256)
 reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               int n_inst, const int64_t* __restrict__ out_offset, int64_t total,
-              const double* __restrict__ Y, const double* __restrict__ partial,
-              OutT* __restrict__ out) {
+              const double* __restrict__ Y, const double* __restrict__ Ylo,
+              const double* __restrict__ partial, OutT* __restrict__ out) {
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total;
        g += (int64_t)gridDim.x * blockDim.x) {
     int lo = 0, hi = n_inst;
@@ -204,6 +228,24 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
     if (C->algo == ALGO_FUSED) {
       const int base = sH * (sH + 1) / 2;
       for (uint32_t UH = 0; UH < nt; ++UH) acc += Yi[(int64_t)UH * Ys + base + __popc(SH & UH)];
+    } else if (Ylo) {
+      // compensated sum of double-doubles (Knuth's TwoSum on the high words,
+      // their errors and the low words summed apart)
+      const double* __restrict__ Li = Ylo + I.yoff + yo;
+      const uint32_t comp = (nt - 1u) & ~SH;
+      uint32_t sub = 0;
+      double c = 0.0;
+      for (;;) {
+        const int64_t o = (int64_t)(SH | sub) * Ys + sH;
+        const double h = Yi[o];
+        const double s1 = acc + h;
+        const double bb = s1 - acc;
+        c += ((acc - (s1 - bb)) + (h - bb)) + Li[o];
+        acc = s1;
+        if (sub == comp) break;
+        sub = (sub - comp) & comp;
+      }
+      acc += c;
     } else {
       const uint32_t comp = (nt - 1u) & ~SH;
       uint32_t sub = 0;
@@ -222,16 +264,55 @@ reduce_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ 
 // per-tile result its output selects (slot |S_H & U| of its s_H block).
 // Outputs past M read entry 0 of the tile (in range) and are never stored
 // by the final pass.
+// For a register-phase instance of several blocks the range is one of
+// blocks: each output adds, for every block H2 and every work item of the
+// block, the partial sum of its (S_L, S_H1, |S_H2|) at j2 = |S_H2 & H2|.
+__device__ __forceinline__ void wide_gather_blocks(const InstDev& I, const WideItem& w, int M,
+                                                   const double* __restrict__ fpart,
+                                                   double* __restrict__ partial) {
+  int32_t pj[kWideK][5];
+  uint32_t s2[kWideK];
+  double acc[kWideK];
+#pragma unroll
+  for (int q = 0; q < kWideK; ++q) {
+    const int k = w.group * kWideOuts + q * 256 + (int)threadIdx.x;
+    const int kk = k < M ? k : 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) pj[q][j] = I.pidx[(int64_t)kk * I.pw + (j < I.pw ? j : 0)];
+    s2[q] = I.osh2[kk];
+    acc[q] = 0.0;
+  }
+  for (int blk = w.t0; blk < w.t1; ++blk) {
+    for (int r = 0; r < I.ipb; ++r) {
+      const double* __restrict__ Pb = fpart + I.pbase + ((int64_t)blk * I.ipb + r) * I.pstride;
+#pragma unroll
+      for (int q = 0; q < kWideK; ++q) {
+        const int j = __popc(s2[q] & (uint32_t)blk);
+        const int32_t o = j == 0 ? pj[q][0] : j == 1 ? pj[q][1] : j == 2 ? pj[q][2]
+                        : j == 3 ? pj[q][3] : pj[q][4];
+        acc[q] += Pb[o];
+      }
+    }
+  }
+  double* P = partial + w.pofs;
+#pragma unroll
+  for (int q = 0; q < kWideK; ++q) P[q * 256 + threadIdx.x] = acc[q];
+}
+
 __global__ void __launch_bounds__(256)
 wide_gather_kernel(const ClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
                    const WideItem* __restrict__ items, int n_items,
                    const int64_t* __restrict__ out_offset, const double* __restrict__ Y,
-                   double* __restrict__ partial) {
+                   const double* __restrict__ fpart, double* __restrict__ partial) {
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const WideItem w = items[it];
     const InstDev I = insts[w.inst];
     const ClassDev* C = classes + I.cls;
     const int M = (int)(out_offset[w.inst + 1] - out_offset[w.inst]);
+    if (I.fast) {
+      wide_gather_blocks(I, w, M, fpart, partial);
+      continue;
+    }
     const int64_t Ys = C->Ysize;
     uint32_t yo[kWideK], sh[kWideK];
     double acc[kWideK];
@@ -298,7 +379,7 @@ fast_reduce_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ c
     const int k = c.y + o;
     double acc = 0.0;
     if (k < M) {
-      const double* P = partial + I.pbase + I.pidx[k];
+      const double* P = partial + I.pbase + I.pidx[(int64_t)k * I.pw];
       for (int j = r; j < I.nitems; j += ROWS) acc += P[(int64_t)j * I.pstride];
     }
     if constexpr (ROWS == 1) {
@@ -466,7 +547,7 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
     if (stage == wfin - 1) {
       hipLaunchKernelGGL(wide_gather_kernel, dim3(a.grid_wide), dim3(256), 0, st, a.classes,
                          a.insts, a.wide_items, a.n_wide_items, a.out_offset, a.Y,
-                         a.wide_partial);
+                         a.partial, a.wide_partial);
       return hipGetLastError();
     }
     if (stage == wfin) {
@@ -481,7 +562,7 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
           : (a.n_generic > 0 &&
              stage == last - (a.n_red_chunks > 0) - 2 * (a.n_wide_items > 0))) {
     hipLaunchKernelGGL(reduce_kernel<InT>, dim3(a.grid_reduce), dim3(256), 0, st, a.classes,
-                       a.insts, a.n_inst, a.out_offset, a.total_out, a.Y, a.partial,
+                       a.insts, a.n_inst, a.out_offset, a.total_out, a.Y, a.Ylo, a.partial,
                        static_cast<InT*>(a.out));
     return hipGetLastError();
   }
@@ -498,7 +579,7 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   if (a.algo == ALGO_FUSED) {
     hipLaunchKernelGGL((tile_kernel<InT, MobT, SwT, true>), dim3(a.grid_tile), dim3(kTileThreads),
                        a.tile_lds, st, a.classes, a.insts, a.tile_items, a.n_tile_items,
-                       static_cast<const InT*>(a.values), a.Y);
+                       static_cast<const InT*>(a.values), a.Y, nullptr);
     return hipGetLastError();
   }
   if (stage == 0) {
@@ -516,7 +597,7 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   }
   hipLaunchKernelGGL((tile_kernel<MobT, MobT, SwT, false>), dim3(a.grid_tile), dim3(kTileThreads),
                      a.tile_lds, st, a.classes, a.insts, a.tile_items, a.n_tile_items,
-                     static_cast<const MobT*>(a.work), a.Y);
+                     static_cast<const MobT*>(a.work), a.Y, a.Ylo);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <unordered_map>
 
 #include "../../include/fsi.h"
 #include "fsi_internal.h"
@@ -230,6 +231,9 @@ std::string build_class(int d, int l, int b, int algo, int index, int mobius_in,
   }
   C->lam_ublock = off;
   C->lam.assign((size_t)(h + 1) * off, 0.0);
+  // two-pass: the weights also as double-doubles (their rounding error,
+  // for the compensated FP64 weight core)
+  if (algo != ALGO_FUSED) C->lam_lo.assign((size_t)(h + 1) * off, 0.0);
   for (int u = 0; u <= h; ++u) {
     for (int sL = 0; sL <= std::min(l, b); ++sL) {
       double* blk = &C->lam[(size_t)u * off + C->lam_soff[sL]];
@@ -253,8 +257,12 @@ std::string build_class(int d, int l, int b, int algo, int index, int mobius_in,
               blk[slot * (b + 1) + tL] = ok ? (double)lambda_q(s, tL, q, u, h, l, index) : 0.0;
           }
         } else {
-          for (int tL = sL; tL <= b; ++tL)
-            blk[sH * (b + 1) + tL] = (double)weight_q(s, tL + u, l, index);
+          double* blo = &C->lam_lo[(size_t)u * off + C->lam_soff[sL]];
+          for (int tL = sL; tL <= b; ++tL) {
+            const __float128 w = weight_q(s, tL + u, l, index);
+            blk[sH * (b + 1) + tL] = (double)w;
+            blo[sH * (b + 1) + tL] = (double)(w - (__float128)(double)w);
+          }
         }
       }
     }
@@ -274,18 +282,21 @@ std::string build_class(int d, int l, int b, int algo, int index, int mobius_in,
   return "";
 }
 
-int fast_max_high_bits(int l) {
-  return (l >= 1 && l <= t11::PA) ? 32 - t11::meta_shift(l) : 0;
+int fast_block_bits(int d, int l) {
+  using namespace t11;
+  if (d < B || l < 1 || l > 4 || l > d) return -1;
+  const int h = d - B, hmax = 32 - meta_shift(l);
+  if (h <= hmax && positions_needed(l, h) <= np_order(l)) return h;
+  for (int k = std::min(h - 1, hmax); k >= 0; --k)
+    if (positions_blocked(l, k) <= np_order(l)) return k;
+  return -1;
 }
 
 int fast_output_slots(int d, int l) {
-  if (d < t11::B || l > 4 || l > d) return -1;
+  const int k = fast_block_bits(d, l);
+  if (k < 0) return -1;
   const int h = d - t11::B;
-  const int64_t pos = t11::positions_needed(l, h);
-  // only order 4 gathers its outputs in several groups
-  if (l < 4 && pos > t11::np_order(l)) return -1;
-  if (pos > (int64_t)1 << 20) return -1;
-  return (int)(2 * pos);
+  return (int)(2 * (k == h ? t11::positions_needed(l, h) : t11::positions_blocked(l, k)));
 }
 
 std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
@@ -295,7 +306,6 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
   if (C.algo != ALGO_FUSED) return "register-phase kernel needs the fused algorithm";
   if (l > 4) return "register-phase kernel needs l <= 4";
   F->mshift = meta_shift(l);
-  if (h > 32 - F->mshift) return "too many high bits for the register-phase kernel";
   F->d = C.d; F->l = l; F->h = h; F->M = C.M; F->mobius_in = C.mobius_in;
   // phase-C units and their maps
   const int nu = n3(l);
@@ -336,24 +346,25 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
                 C.lam[(size_t)u * C.lam_ublock + C.lam_soff[sL] + slot * (b + 1) + sL + r];
         }
     }
-  // outputs: runs of two outputs (S_L of ranks 2r and 2r + 1 among the S_L
-  // of one size, one S_H). Runs are taken by |S_L| (descending), then S_H,
-  // then r, and dealt to wave units: unit u is position u / 4 of wave u % 4
-  // of the workgroup, 64 runs of one |S_L| (so the j-stride is uniform in a
-  // wave); a unit left short by its |S_L| is filled with dummy runs (offset
-  // 0, S_H = 0: a valid read whose sums nothing uses). Output group g takes
-  // the units of positions [g kRuns, (g + 1) kRuns).
-  const int total = fast_output_slots(C.d, l);
-  if (total < 0) return "register-phase kernel does not apply";
-  const int npos = total / 2;
-  F->ngroups = (npos + kRuns - 1) / kRuns;
-  // only order 4 has a grouped kernel instantiation
-  if (F->ngroups > 1 && l != kFastMaxL) return "output groups are only built for l = 4";
+  // partial sums: runs of two (S_L of ranks 2r and 2r + 1 among the S_L of
+  // one size), taken by |S_L| (descending), then by what the run sums over
+  // the high bits, then r, and dealt to wave units: unit u is position u / 4
+  // of wave u % 4 of the workgroup, 64 runs of one |S_L| (so the j-stride is
+  // uniform in a wave); a unit left short by its |S_L| is filled with dummy
+  // runs (offset 0, S_H = 0: a valid read whose sums nothing uses).
+  //  - whole instance (kb = h): a run is one S_H; it sums, over the tiles,
+  //    Y[S_L, |S_H|, |S_H & U_H|], an output.
+  //  - blocks (kb < h): a run is (S_H1 over the kb low high bits, s_H2, j2);
+  //    it sums Y[S_L, |S_H1| + s_H2, |S_H1 & U_H| + j2] over the block.
+  const int kb = fast_block_bits(C.d, l);
+  if (kb < 0) return "register-phase kernel does not apply";
+  F->kb = kb;
+  const bool blocked = kb < h;
+  const int npos = fast_output_slots(C.d, l) / 2;
+  if (npos > np_order(l)) return "gather positions exceed the kernel's";
   if (kRuns != kFastRuns) return "gather position count mismatch";
   const size_t M = C.out_masks.size();
   const uint32_t lowmask = (1u << b) - 1;
-  std::map<uint64_t, int> canon;
-  for (size_t k = 0; k < M; ++k) canon[C.out_masks[k]] = (int)k;
   // S_L of each size in colex rank order
   std::vector<std::vector<uint32_t>> low(l + 1);
   for (uint32_t m = 0; m <= lowmask; ++m) {
@@ -365,54 +376,66 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
               [](uint32_t x, uint32_t y) { return rank_colex(x) < rank_colex(y); });
     if ((int)low[sL].size() != cbinom(B, sL)) return "low output count mismatch";
   }
-  // S_H of each size
+  // high masks (over the kb low high bits) of each size
   std::vector<std::vector<uint32_t>> high(l + 1);
-  for (uint32_t m = 0; m < (1u << h); ++m) {
+  for (uint32_t m = 0; m < (1u << kb); ++m) {
     const int sH = popc(m);
     if (sH <= l) high[sH].push_back(m);
   }
-  F->meta.assign((size_t)F->ngroups * kFastThreads * kFastMetaStride, 0u);
-  F->gs8.assign((size_t)F->ngroups * kRuns * 4, 0u);
-  F->gnkk.assign(F->ngroups, 0);
-  F->pidx.assign(M, -1);
-  F->pgroup.assign(M, -1);
+  F->meta.assign((size_t)kFastThreads * kFastMetaStride, 0u);
+  F->gs8.assign((size_t)kRuns * 4, 0u);
+  F->nkk = 0;
+  // slot of (S_L, S_H1, s_H2, j2), key S_L | S_H1 << 11 | (s_H2 * 8 + j2) << 40
+  std::unordered_map<uint64_t, int32_t> slot_of;
+  slot_of.reserve((size_t)npos * 4 * 64 * 2);
+  auto key = [](uint32_t SL, uint32_t S1, int s2, int j2) {
+    return (uint64_t)SL | ((uint64_t)S1 << 11) | ((uint64_t)(s2 * 8 + j2) << 40);
+  };
   int64_t unit = 0;
   for (int sL = l; sL >= 0; --sL) {
     const uint32_t nr = (uint32_t)cbinom(B, sL);
     int lane = 64;   // start a new unit for each |S_L|
-    for (int sH = 0; sH <= std::min(l - sL, h); ++sH)
-      for (uint32_t SH : high[sH])
-        for (uint32_t r0 = 0; r0 < nr; r0 += 2) {
-          if (lane == 64) {
-            lane = 0;
-            ++unit;
-          }
-          const int64_t u = unit - 1;
-          const int pos = (int)(u / 4), w = (int)(u % 4);
-          const int g = pos / kRuns, p = pos % kRuns, t = 64 * w + lane;
-          if (g >= F->ngroups) return "gather unit past the last group";
-          F->gs8[((size_t)g * kRuns + p) * 4 + w] = (uint32_t)nrp(sL) * 8u;
-          F->gnkk[g] = std::max(F->gnkk[g], 2 * (p + 1));
-          const uint32_t A =
-              (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * nrp(sL) + (int)r0);
-          if (A * 8 >= (1u << F->mshift) || (uint64_t)SH >= (1ull << (32 - F->mshift)))
-            return "output metadata overflow";
-          F->meta[((size_t)g * kFastThreads + t) * kFastMetaStride + p] = (A * 8) | (SH << F->mshift);
-          for (uint32_t e = 0; e < 2; ++e) {
-            if (r0 + e >= nr) break;
-            const uint32_t S = low[sL][r0 + e] | (SH << b);
-            auto it = canon.find(S);
-            if (it == canon.end()) return "run output outside the canonical set";
-            F->pidx[it->second] = (int)(2 * p + e) * kFastThreads + t;
-            F->pgroup[it->second] = g;
-          }
-          ++lane;
-        }
+    for (int a = 0; a <= std::min(l - sL, kb); ++a)
+      for (uint32_t S1 : high[a])
+        for (int s2 = 0; s2 <= (blocked ? l - sL - a : 0); ++s2)
+          for (int j2 = 0; j2 <= s2; ++j2)
+            for (uint32_t r0 = 0; r0 < nr; r0 += 2) {
+              if (lane == 64) {
+                lane = 0;
+                ++unit;
+              }
+              const int64_t u = unit - 1;
+              const int pos = (int)(u / 4), w = (int)(u % 4), t = 64 * w + lane;
+              if (pos >= npos) return "gather unit past the last position";
+              F->gs8[(size_t)pos * 4 + w] = (uint32_t)nrp(sL) * 8u;
+              F->nkk = std::max(F->nkk, 2 * (pos + 1));
+              const int sH = a + s2;
+              const uint32_t A =
+                  (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2 + j2) * nrp(sL) + (int)r0);
+              if (A * 8 >= (1u << F->mshift) || (uint64_t)S1 >= (1ull << (32 - F->mshift)))
+                return "output metadata overflow";
+              F->meta[(size_t)t * kFastMetaStride + pos] = (A * 8) | (S1 << F->mshift);
+              for (uint32_t e = 0; e < 2 && r0 + e < nr; ++e)
+                slot_of[key(low[sL][r0 + e], S1, s2, j2)] = (int32_t)((2 * pos + e) * kFastThreads + t);
+              ++lane;
+            }
   }
-  for (size_t k = 0; k < M; ++k)
-    if (F->pidx[k] < 0) return "an output has no run";
-  F->nkk = 0;
-  for (int g = 0; g < F->ngroups; ++g) F->nkk = std::max(F->nkk, F->gnkk[g]);
+  // each canonical output's slots, j2 = 0 .. l (whole instances: j2 = 0)
+  F->pidx.assign(M * (size_t)(l + 1), -1);
+  F->osh2.assign(M, 0u);
+  const uint32_t lowhigh = (uint32_t)((1ull << kb) - 1);
+  for (size_t k = 0; k < M; ++k) {
+    const uint32_t S = C.out_masks[k];
+    const uint32_t SL = S & lowmask, SH = S >> b;
+    const uint32_t S1 = SH & lowhigh, S2 = blocked ? SH >> kb : 0u;
+    const int s2 = popc(S2);
+    F->osh2[k] = S2;
+    for (int j2 = 0; j2 <= l; ++j2) {
+      auto it = slot_of.find(key(SL, S1, s2, std::min(j2, s2)));
+      if (it == slot_of.end()) return "an output has no slot";
+      F->pidx[k * (size_t)(l + 1) + j2] = it->second;
+    }
+  }
   return "";
 }
 

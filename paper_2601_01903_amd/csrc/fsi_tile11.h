@@ -242,11 +242,31 @@ constexpr int meta_shift(int L) {
   while ((1 << s) <= ysize(L) * 8) ++s;
   return s;
 }
-constexpr int kMaxH = 32 - meta_shift(3);
+
+// ---- blocked outputs: when an instance has more outputs than the
+// workgroup's accumulators hold, a work item covers a block of 2^k tiles
+// sharing their top h - k high bits H2 = U_H >> k, and its partial sums are
+//   Y2[S_L, S_H1, s_H2, j2] = sum over the block's tiles of
+//                             Y[S_L, |S_H1| + s_H2, |S_H1 & U_H| + j2]
+// for S_H1 within the k low high bits; the reduction picks j2 = |S_H2 & H2|
+// for an output with S_H = S_H1 | S_H2 << k and s_H2 = |S_H2|. The gather
+// is the same as for whole instances: S_H1 in the metadata word, the
+// (s_H2, j2) part folded into the Y offset.
+constexpr int64_t tri(int n) { return (int64_t)(n + 1) * (n + 2) / 2; }
+constexpr int64_t runs_blocked(int L, int k, int sL) {
+  int64_t c = 0;
+  for (int a = 0; a <= L - sL && a <= k; ++a) c += (int64_t)cbinom(k, a) * tri(L - sL - a);
+  return (int64_t)((cbinom(B, sL) + 1) / 2) * c;
+}
+constexpr int64_t positions_blocked(int L, int k) {
+  int64_t units = 0;
+  for (int sL = 0; sL <= L; ++sL) units += (runs_blocked(L, k, sL) + 63) / 64;
+  return (units + 3) / 4;
+}
 
 // gather positions per thread; the kernel of order L unrolls np_order(L) of
 // them (the most its outputs need at any h the metadata word holds, at most
-// kRuns; past that only order 4 splits its outputs into groups)
+// kRuns; past that the outputs are blocked)
 constexpr int kRuns = 14;
 constexpr int np_order(int L) {
   int64_t m = 0;

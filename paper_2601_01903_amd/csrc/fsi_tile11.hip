@@ -569,7 +569,7 @@ constexpr int prio_c(int w) {
 constexpr int kPrioTwoWave = 1;
 
 // ------------------------------------------------------------------ item
-template <int L, typename SwT, typename MobT, bool IN64, bool GROUPED, bool MOBIN>
+template <int L, typename SwT, typename MobT, bool IN64, bool MOBIN>
 __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, const InstDev& I,
                                          const FastItem& W, const float* __restrict__ vals32,
                                          const double* __restrict__ vals64,
@@ -611,14 +611,10 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   double acc[KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) acc[k] = 0.0;
-  // output group of the item (instances whose outputs need more than
-  // kFastKmax slots per thread are gathered in several groups)
-  const int grp = GROUPED ? __builtin_amdgcn_readfirstlane(W.group) : 0;
-  const uint4* meta_g =
-      reinterpret_cast<const uint4*>(C->meta + ((size_t)grp * NT + tid) * kFastMetaStride);
+  const uint4* meta_g = reinterpret_cast<const uint4*>(C->meta + (size_t)tid * kFastMetaStride);
   // j-stride of Y per (position, wave)
-  const cdptr_u gs8 = (cdptr_u)(C->gs8 + (grp * kRuns) * 4 + wave);
-  const int nkk = GROUPED ? C->gnkk[grp] : C->nkk;
+  const cdptr_u gs8 = (cdptr_u)(C->gs8 + wave);
+  const int nkk = C->nkk;
   // input already Moebius-transformed (a separate instantiation): the
   // butterflies are skipped
   constexpr bool mob = !MOBIN;
@@ -629,14 +625,23 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
   const int64_t vbase = I.voff;
   using RawT = typename std::conditional<IN64, double, float>::type;
   RawT xraw[NC];   // next tile's raw values (converted when its butterfly starts)
+  // an instance with d < 11 (lowmask = 2^d - 1) runs as d = 11: the value
+  // of U is v(U & lowmask), and its Moebius coefficients past bit d - 1
+  // are zero (Moebius input)
+  const int lowmask = I.lowmask;
   auto load_tile = [&](int UH) {
-    const int64_t base = vbase + ((int64_t)UH << B) + tid;
+    const int64_t base = vbase + ((int64_t)UH << B);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      if constexpr (IN64)
-        xraw[c] = vals64[base + (c << 8)];
-      else
-        xraw[c] = vals32[base + (c << 8)];
+      const int idx = tid + (c << 8);
+      const int64_t at = base + (idx & lowmask);
+      if constexpr (MOBIN) {
+        if constexpr (IN64) xraw[c] = idx <= lowmask ? vals64[at] : 0.0;
+        else xraw[c] = idx <= lowmask ? vals32[at] : 0.f;
+      } else {
+        if constexpr (IN64) xraw[c] = vals64[at];
+        else xraw[c] = vals32[at];
+      }
     }
   };
   int UH = torder[I.tofs + W.tb];
@@ -834,7 +839,7 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
 // One kernel per order l (the items of a launch all have that order).
 // FP32 sweep: two workgroups per CU (2 waves per SIMD), so at most 256 VGPRs
 // per thread; the FP64 sweep's LDS allows one workgroup per CU.
-template <int L, typename SwT, typename MobT, bool IN64, int WPE, bool GROUPED, bool MOBIN>
+template <int L, typename SwT, typename MobT, bool IN64, int WPE, bool MOBIN>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               const FastItem* __restrict__ items, int n_items,
@@ -850,17 +855,16 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
   for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
-    run_item<L, SwT, MobT, IN64, GROUPED, MOBIN>(classes + I.fcls, I, W, vals32, vals64, torder, partial,
-                                          smem);
+    run_item<L, SwT, MobT, IN64, MOBIN>(classes + I.fcls, I, W, vals32, vals64, torder, partial,
+                                        smem);
     __syncthreads();
   }
 }
 
 // Items of every order in one launch (a batch of instances with different
 // l): each item runs the code compiled for its instance's order; the
-// regions of all orders share one allocation (LdsAll). Order-4 items use the
-// grouped code when GROUPED4 is set.
-template <typename SwT, typename MobT, bool IN64, int WPE, bool GROUPED4, bool MOBIN>
+// regions of all orders share one allocation (LdsAll).
+template <typename SwT, typename MobT, bool IN64, int WPE, bool MOBIN>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
                     const FastItem* __restrict__ items, int n_items,
@@ -879,10 +883,10 @@ tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __r
     const FastClassDev* C = classes + I.fcls;
     const int l = __builtin_amdgcn_readfirstlane(C->l);
     switch (l) {
-      case 1: run_item<1, SwT, MobT, IN64, false, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
-      case 2: run_item<2, SwT, MobT, IN64, false, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
-      case 3: run_item<3, SwT, MobT, IN64, false, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
-      default: run_item<4, SwT, MobT, IN64, GROUPED4, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 1: run_item<1, SwT, MobT, IN64, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 2: run_item<2, SwT, MobT, IN64, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      case 3: run_item<3, SwT, MobT, IN64, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
+      default: run_item<4, SwT, MobT, IN64, MOBIN>(C, I, W, vals32, vals64, torder, partial, smem); break;
     }
     __syncthreads();
   }
@@ -900,17 +904,13 @@ constexpr int lds_bytes_for(int) {
 // ------------------------------------------------------------------ launcher
 template <typename SwT> constexpr int wpe_for() { return sizeof(SwT) == 4 ? 2 : 1; }
 
-// Output groups occur only at l = 4 (lower orders need at most 20 slots
-// per thread), so only that order has a grouped instantiation; a launch
-// uses it when one of its instances has more than one group. Plans whose
-// input is already the Moebius transform run their own instantiations.
+// Plans whose input is already the Moebius transform run their own
+// instantiations.
 template <int L, typename SwT, typename MobT, bool IN64, bool MOBIN>
 static hipError_t launch_t11_m(const FastLaunch& f, hipStream_t st) {
   const int ib = f.lbeg[L], n = f.lbeg[L + 1] - f.lbeg[L];
   if (n <= 0) return hipSuccess;
-  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
-  if constexpr (L == kFastMaxL)
-    if (f.grouped[L]) k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>;
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), MOBIN>;
   hipLaunchKernelGGL(k, dim3(f.grid[L]), dim3(t11::NT), f.lds[L], st, f.classes, f.insts,
                      f.items + ib, n, static_cast<const float*>(f.vals32),
                      static_cast<const double*>(f.vals64), f.torder, f.partial);
@@ -925,16 +925,9 @@ static hipError_t launch_t11(const FastLaunch& f, hipStream_t st) {
 
 template <int L, typename SwT, typename MobT, bool IN64, bool MOBIN>
 static hipError_t config_t11_m(size_t lds) {
-  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if constexpr (L == kFastMaxL) {
-    if (e != hipSuccess) return e;
-    auto kg = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>;
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kg),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  }
-  return e;
+  auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), MOBIN>;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <int L, typename SwT, typename MobT, bool IN64>
@@ -947,8 +940,7 @@ static hipError_t config_t11(size_t lds) {
 // One launch over the items of every order (the plan has several orders).
 template <typename SwT, typename MobT, bool IN64, bool MOBIN>
 static hipError_t launch_mixed_m(const FastLaunch& f, hipStream_t st) {
-  auto k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
-  if (f.grouped[kFastMaxL]) k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>;
+  auto k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), MOBIN>;
   hipLaunchKernelGGL(k, dim3(f.grid_mixed), dim3(t11::NT), f.lds_mixed, st, f.classes, f.insts,
                      f.items, f.n_items, static_cast<const float*>(f.vals32),
                      static_cast<const double*>(f.vals64), f.torder, f.partial);
@@ -963,14 +955,9 @@ static hipError_t launch_mixed_t(const FastLaunch& f, hipStream_t st) {
 
 template <typename SwT, typename MobT, bool IN64, bool MOBIN>
 static hipError_t config_mixed_m(size_t lds) {
-  for (int g = 0; g < 2; ++g) {
-    auto k = g ? t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), true, MOBIN>
-               : t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), false, MOBIN>;
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  auto k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), MOBIN>;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 template <typename SwT, typename MobT, bool IN64>

@@ -2,6 +2,7 @@
 // paper_2601_01903_amd/csrc/fsi_tables.cpp), run on the CPU by
 // tests/test_host_tables.py. Prints "ok" or the first violation.
 #include <cstdio>
+#include <map>
 #include <set>
 #include <string>
 #include <vector>
@@ -77,13 +78,20 @@ int main() {
           }
     for (int u = 0; u < n3(L); ++u) CHECK(count[u] == 1, "L=%d unit %d taken %d times", L, u, count[u]);
   }
-  // every eligible (d, l): tables build, each canonical output decodes to its
-  // own mask from the metadata word, and the slots are a bijection
+  // every (d, l): tables build; each canonical output's slots (j2 = 0 ..
+  // |S_H2|; whole instances: j2 = 0) decode from the metadata word to its
+  // own S_L, S_H1 and Y offset; distinct (S_L, S_H1, s_H2, j2) take distinct
+  // slots; every read stays inside Y
   for (int l = 1; l <= 4; ++l)
     for (int d = 11; d <= 30; ++d) {
+      const int kb = fast_block_bits(d, l), h = d - 11;
+      CHECK(kb >= 0 && kb <= h, "d=%d l=%d: no block size", d, l);
+      if (kb < 0) continue;
       const int slots = fast_output_slots(d, l);
-      const bool eligible = slots >= 0 && d - 11 <= fast_max_high_bits(l);
-      if (!eligible) continue;
+      const bool blocked = kb < h;
+      if (blocked)
+        CHECK(positions_needed(l, h) > np_order(l) || h > 32 - meta_shift(l),
+              "d=%d l=%d: blocked although the outputs fit", d, l);
       ClassHost C;
       FastClassHost F;
       std::string e = build_class(d, l, 11, ALGO_FUSED, 0, 0, &C);
@@ -92,53 +100,54 @@ int main() {
       e = build_fast_class(C, &F);
       CHECK(e.empty(), "d=%d l=%d build_fast_class: %s", d, l, e.c_str());
       if (!e.empty()) continue;
-      // runs of two outputs: 2 slots per gather position, kRuns positions per group
       const int npos = slots / 2;
-      CHECK(slots % 2 == 0 && npos == positions_needed(l, d - 11), "d=%d l=%d: %d slots", d, l, slots);
-      CHECK(F.ngroups == (npos + kRuns - 1) / kRuns, "d=%d l=%d: %d output groups", d, l, F.ngroups);
-      CHECK(l == 4 || npos <= np_order(l), "d=%d l=%d: %d positions, kernel unrolls %d", d, l, npos,
-            np_order(l));
-      for (int g = 0; g < F.ngroups; ++g)
-        CHECK(F.gnkk[g] >= 2 && F.gnkk[g] <= 2 * kRuns && F.gnkk[g] % 2 == 0,
-              "d=%d l=%d group %d: %d slots", d, l, g, F.gnkk[g]);
+      CHECK(F.kb == kb, "d=%d l=%d: block bits %d, expected %d", d, l, F.kb, kb);
+      CHECK(slots % 2 == 0 && npos == (blocked ? positions_blocked(l, kb) : positions_needed(l, h)),
+            "d=%d l=%d: %d slots", d, l, slots);
+      CHECK(npos <= np_order(l), "d=%d l=%d: %d positions, kernel unrolls %d", d, l, npos, np_order(l));
+      CHECK(F.nkk >= 2 && F.nkk <= 2 * npos && F.nkk % 2 == 0, "d=%d l=%d: %d slots in use", d, l, F.nkk);
       const uint32_t omask = (1u << F.mshift) - 1u;
-      std::set<int> used;
+      const uint32_t lowhigh = (uint32_t)((1ull << kb) - 1);
+      std::map<int, uint64_t> owner;   // slot -> (S_L, S_H1, s_H2, j2)
       for (size_t k = 0; k < C.out_masks.size(); ++k) {
-        const int p = F.pidx[k], g = F.pgroup[k];
-        CHECK(g >= 0 && g < F.ngroups, "d=%d l=%d output %zu: group out of range", d, l, k);
-        if (g < 0 || g >= F.ngroups) continue;
-        CHECK(p >= 0 && p < F.gnkk[g] * kFastThreads, "d=%d l=%d output %zu: slot out of range", d, l, k);
-        CHECK(used.insert(g * kFastKmax * kFastThreads + p).second, "d=%d l=%d: slot used twice", d, l);
-        const int kk = p / kFastThreads, t = p % kFastThreads;
-        const int pos = kk / 2, e = kk % 2, w = t / 64;
-        const uint32_t m = F.meta[((size_t)g * kFastThreads + t) * kFastMetaStride + pos];
         const uint32_t S = C.out_masks[k];
         const uint32_t SL = S & 0x7FFu, SH = S >> 11;
-        CHECK((m >> F.mshift) == SH, "d=%d l=%d output %zu: S_H decodes wrongly", d, l, k);
-        // the run's Y offset at j = 0 addresses (S_L of the even rank, s_H):
-        // group base plus the pair's first rank; this output is element e
-        const int sL = cpop((int)SL), sH = cpop((int)SH);
+        const uint32_t S1 = SH & lowhigh, S2 = blocked ? SH >> kb : 0u;
+        CHECK(F.osh2[k] == S2, "d=%d l=%d output %zu: S_H2 %u", d, l, k, F.osh2[k]);
+        const int sL = cpop((int)SL), s1 = cpop((int)S1), s2 = cpop((int)S2);
         const int rk = rank_colex(SL);
-        CHECK(rk % 2 == e, "d=%d l=%d output %zu: rank parity %d in element %d", d, l, k, rk, e);
-        const uint32_t want =
-            (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2) * nrp(sL) + rk - e) * 8u;
-        CHECK((m & omask) == want, "d=%d l=%d output %zu: Y offset decodes wrongly", d, l, k);
-        CHECK(want % 16 == 0, "d=%d l=%d output %zu: read not 16-byte aligned", d, l, k);
-        const uint32_t gs = F.gs8[((size_t)g * kRuns + pos) * 4 + w];
-        CHECK(gs == (uint32_t)nrp(sL) * 8u, "d=%d l=%d: j stride of position %d wave %d", d, l, pos, w);
-        CHECK((m & omask) + (uint32_t)sH * gs + 16 <= (uint32_t)ysize(l) * 8u,
-              "d=%d l=%d output %zu: Y read past the tile's results", d, l, k);
+        for (int j2 = 0; j2 <= l; ++j2) {
+          const int jj = j2 < s2 ? j2 : s2;
+          const int p = F.pidx[k * (size_t)(l + 1) + j2];
+          CHECK(p >= 0 && p < F.nkk * kFastThreads, "d=%d l=%d output %zu: slot out of range", d, l, k);
+          if (p < 0 || p >= F.nkk * kFastThreads) continue;
+          const uint64_t key = (uint64_t)SL | ((uint64_t)S1 << 11) | ((uint64_t)(s2 * 8 + jj) << 40);
+          auto it = owner.find(p);
+          if (it == owner.end()) owner[p] = key;
+          else CHECK(it->second == key, "d=%d l=%d: slot %d shared by two partial sums", d, l, p);
+          const int kk = p / kFastThreads, t = p % kFastThreads;
+          const int pos = kk / 2, el = kk % 2, w = t / 64;
+          const uint32_t m = F.meta[(size_t)t * kFastMetaStride + pos];
+          CHECK((m >> F.mshift) == S1, "d=%d l=%d output %zu: S_H1 decodes wrongly", d, l, k);
+          CHECK(rk % 2 == el, "d=%d l=%d output %zu: rank parity %d in element %d", d, l, k, rk, el);
+          const int sH = s1 + s2;
+          const uint32_t want =
+              (uint32_t)(ybase(l, sL) + (sH * (sH + 1) / 2 + jj) * nrp(sL) + rk - el) * 8u;
+          CHECK((m & omask) == want, "d=%d l=%d output %zu: Y offset decodes wrongly", d, l, k);
+          CHECK(want % 16 == 0, "d=%d l=%d output %zu: read not 16-byte aligned", d, l, k);
+          const uint32_t gs = F.gs8[(size_t)pos * 4 + w];
+          CHECK(gs == (uint32_t)nrp(sL) * 8u, "d=%d l=%d: j stride of position %d wave %d", d, l, pos, w);
+        }
       }
-      // every run's read (real or dummy) stays inside Y for every j
-      for (int g = 0; g < F.ngroups; ++g)
-        for (int t = 0; t < kFastThreads; ++t)
-          for (int pos = 0; pos < kRuns; ++pos) {
-            const uint32_t m = F.meta[((size_t)g * kFastThreads + t) * kFastMetaStride + pos];
-            const uint32_t gs = F.gs8[((size_t)g * kRuns + pos) * 4 + t / 64];
-            const int sH = cpop((int)(m >> F.mshift));
-            CHECK((m & omask) % 16 == 0 && (m & omask) + (uint32_t)sH * gs + 16 <= (uint32_t)ysize(l) * 8u,
-                  "d=%d l=%d group %d thread %d position %d: read out of Y", d, l, g, t, pos);
-          }
+      // every run's read (real or dummy) stays inside Y for every j1 <= |S_H1|
+      for (int t = 0; t < kFastThreads; ++t)
+        for (int pos = 0; pos < kRuns; ++pos) {
+          const uint32_t m = F.meta[(size_t)t * kFastMetaStride + pos];
+          const uint32_t gs = F.gs8[(size_t)pos * 4 + t / 64];
+          const int s1 = cpop((int)(m >> F.mshift));
+          CHECK((m & omask) % 16 == 0 && (m & omask) + (uint32_t)s1 * gs + 16 <= (uint32_t)ysize(l) * 8u,
+                "d=%d l=%d thread %d position %d: read out of Y", d, l, t, pos);
+        }
       CHECK((int)F.lam.size() == (F.h + 1) * lamblock(l), "d=%d l=%d: weight block size", d, l);
     }
   std::printf(fails ? "failures: %d\n" : "ok\n", fails);

@@ -114,11 +114,11 @@ def test_unknown_index_rejected():
 
 
 @pytest.mark.parametrize("index", ["ksii", "sii"])
-def test_index_grouped_register_kernel(index):
-    """d = 22, l = 4 runs the register-phase kernel with two output groups."""
+def test_index_blocked_register_kernel(index):
+    """d = 22, l = 4 runs the register-phase kernel in blocks of 2^6 tiles."""
     fsi = fsi_mod()
     d, l = 22, 4
-    say(f"[case] index={index} d={d} l={l} FP32, output groups")
+    say(f"[case] index={index} d={d} l={l} FP32, blocks")
     g = games.tree_game(d, 60, 5, games.rng_for(505, 0))
     v32 = games.tree_values(g).astype(np.float32)
     plan = fsi.Plan(d, l, dtype="f32", index=index)

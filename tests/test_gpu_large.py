@@ -1,8 +1,8 @@
 """The operator at the largest sizes one MI355X holds in core (d = 26 to 30;
 the paper's own method stops near d = 25 for memory). FP32 storage, on the
-register-phase kernel (at l = 4 past d = 20 with its outputs split into
-groups, each gathered by its own pass over the tiles) and, past its limits,
-on the generic kernel.
+register-phase kernel (at l = 4 past d = 20 in blocks of 2^6 tiles whose
+partial sums the wide gather combines).
+
 
 d = 26 and 28: sampled outputs against the C oracle, which evaluates only the
 requested outputs (its Moebius transform still covers all 2^d values).
@@ -35,8 +35,8 @@ def integer_planted(d, n_terms, kmax, seed):
 def run(d, l, v32, precision="f32_compensated"):
     from paper_2601_01903_amd import fsi
     plan = fsi.Plan(d, l, dtype="f32", precision=precision)
-    # the register-phase kernel holds up to 25, 22, 20, 18 high bits at l = 1..4
-    assert plan.schedule()["fast_instances"] == (1 if d - 11 <= {1: 25, 2: 22, 3: 20, 4: 18}[l] else 0)
+    # the register-phase kernel takes every d <= 30 at l <= 4
+    assert plan.schedule()["fast_instances"] == 1
     out = plan.apply(torch.from_numpy(v32).to(DEV))
     torch.cuda.synchronize()
     res = out.double().cpu().numpy()
@@ -91,9 +91,9 @@ def _planted32(d):
 
 @pytest.mark.parametrize("d,l", [(29, 4), (30, 2), (30, 3), (30, 4)])
 def test_max_d_planted_closed_form(d, l):
-    """The largest instances: d = 29 at l = 4 (the register-phase kernel's
-    limit there, four output groups), d = 30 at l = 2, 3 (register-phase
-    kernel) and at l = 4 (generic kernel with the wide gather)."""
+    """The largest instances: d = 29 and 30 at l = 4 (register-phase kernel,
+    2^12 and 2^13 blocks of 2^6 tiles), d = 30 at l = 2, 3 (register-phase
+    kernel, the whole instance one block)."""
     say(f"[case] large d={d} l={l} FP32 planted, closed form")
     g, v32 = _planted32(d)
     got = run(d, l, v32)
@@ -141,4 +141,33 @@ def test_wide_gather_in_a_mixed_batch():
     for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
         ref = oracle.fsi_c(v.astype(np.float64), d, l, nthreads=16)
         assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], ref) < 1e-6, (i, d, l)
+    bp.close()
+
+
+def test_blocked_register_kernel_in_a_batch():
+    """A batch that mixes register-phase instances of several blocks (d = 21,
+    22 at l = 4: blocks of 2^6 tiles, reduced by the wide gather), a one-block
+    instance (d = 20, l = 4), register-phase instances at d = 9 (run as
+    d = 11) and d = 13, and a generic one (l = 5): FP64 integer input against
+    the exact oracle at 1e-12, two graph replays with eager work between them
+    bitwise equal to the eager apply."""
+    from paper_2601_01903_amd import fsi
+    ds, ls = [21, 20, 22, 9, 13, 12], [4, 4, 4, 3, 2, 5]
+    say(f"[case] blocked register kernel in a batch {list(zip(ds, ls))}")
+    vals = [np.random.default_rng(933 + i).integers(-3, 4, size=1 << d).astype(np.float64)
+            for i, d in enumerate(ds)]
+    x = torch.from_numpy(np.concatenate(vals)).to(DEV)
+    bp = fsi.BatchPlan(ds, ls, dtype="f64", precision="f64")
+    assert bp.schedule()["fast_instances"] == 5
+    eager = bp.apply(x, graph=False).cpu().numpy()
+    reps = []
+    for _ in range(2):
+        reps.append(bp.apply(x, graph=True).cpu().numpy())
+        torch.cuda.synchronize()
+        (x * 2.0).sum().item()      # eager work between the replays
+    for r in reps:
+        assert np.array_equal(r, eager)
+    for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
+        ref = oracle.fsi_exact_int(v, d, l, nthreads=16)
+        assert normwise(eager[bp.out_offset[i]:bp.out_offset[i + 1]], ref) < 1e-12, (i, d, l)
     bp.close()

@@ -47,7 +47,7 @@ def test_mobius_input_fp64(kernel, d, l):
 
 
 @pytest.mark.parametrize("prec", ["f32_fp64mob", "f32_compensated", "f32"])
-def test_mobius_input_fp32_and_groups(prec):
+def test_mobius_input_fp32_and_blocks(prec):
     for d, l in ((20, 4), (22, 4)):
         say(f"[case] Moebius input d={d} l={l} FP32 {prec}")
         g = games.tree_game(d, 60, 5, games.rng_for(941, d))

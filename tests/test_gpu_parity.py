@@ -19,10 +19,12 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 # Tolerance for cancellation-heavy integer inputs (random small integers,
-# +/-1) against the exact-integer oracle: the two-pass path rounds products of
-# full-range Moebius values with the weights, an error of u * sum |W a(T)|
-# (see test_d20_fp64); the fused path stays at 1e-12.
-INT_TOL = {"fused": 1e-12, "two_pass": 1e-10}
+# +/-1) against the exact-integer oracle. Both FP64 paths hold 1e-12: the
+# fused one weights in-tile Moebius values (|a| <= 2^11), the two-pass one
+# (full-range Moebius values, |a(T)| up to 2^|T|, before the cross-tile sum)
+# keeps its per-tile results as double-doubles from a compensated dot product
+# and adds them with compensated summation (see test_d20_fp64).
+INT_TOL = {"fused": 1e-12, "two_pass": 1e-12}
 
 
 def fsi_mod():
@@ -80,11 +82,11 @@ def test_d20_fp64(l, algo):
     err = normwise(got, oracle.fsi_exact_int(vp, 20, l, nthreads=8))
     say(f"  +/-1 err vs exact {err:.3e}")
     # The two-pass path multiplies full-range Moebius values (|a(T)| up to
-    # 2^|T|) by the weights before the cross-tile sum, so its rounding error
-    # is u * sum |W a(T)|, the same level as any FP64 summation of this
-    # cancellation-heavy sum (the FP64 oracle itself is off by 4.2e-11 here).
-    # The fused path weights in-tile Moebius values (|a| <= 2^12) and stays
-    # within 1e-12.
+    # 2^|T|) by the weights before the cross-tile sum, a cancellation-heavy
+    # sum (the plain FP64 oracle itself is off by 4.2e-11 here): its per-tile
+    # results are double-doubles and the cross-tile sum is compensated, so it
+    # holds 1e-12 like the fused path, which weights in-tile Moebius values
+    # (|a| <= 2^11).
     assert err < INT_TOL[algo]
 
 
@@ -174,13 +176,44 @@ def test_register_kernel_fp64_exact(d, l, kernel):
 @pytest.mark.parametrize("d,l", [(21, 3), (22, 2), (23, 1), (22, 3), (21, 4), (22, 4)])
 def test_register_kernel_wide_high_part(d, l):
     """Up to 12 high bits (2^12 tiles per instance); at l = 4 past d = 20 the
-    outputs need more slots than a thread holds and are split into output
-    groups, each gathered by its own work items."""
+    outputs need more slots than a workgroup holds: work items cover blocks
+    of 2^6 tiles and the wide gather adds the blocks' partial sums."""
     say(f"[case] wide high part d={d} l={l}")
     v = np.random.default_rng(5000 + d * 7 + l).integers(-3, 4, size=1 << d).astype(np.float64)
     got, info = gpu_apply(v, d, l)
     say(f"  tile_bits={info['tile_bits']}")
     assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=16)) < 1e-12
+
+
+def test_register_kernel_small_d():
+    """d < 11 on the register-phase kernel: the instance runs as d = 11 with
+    the value of U taken as v(U & (2^d - 1)) (players past d ignored, so the
+    Moebius coefficients vanish on every set holding one and the weights do
+    not depend on d). Every (d, l) with d <= 10, l <= min(4, d): FP64 integer
+    input against the exact oracle; Moebius input (zero past bit d - 1)
+    against the oracle from the coefficients; FP32 storage of a tree game
+    against the FP64 oracle."""
+    fsi = fsi_mod()
+    for d in range(1, 11):
+        for l in range(1, min(4, d) + 1):
+            say(f"[case] register kernel small d={d} l={l}")
+            v = np.random.default_rng(5200 + 16 * d + l).integers(-4, 5, size=1 << d).astype(np.float64)
+            plan = fsi.Plan(d, l, kernel="register")
+            assert plan.schedule()["fast_instances"] == 1
+            got = plan.apply(torch.as_tensor(v).to(DEV)).cpu().numpy()
+            plan.close()
+            assert normwise(got, oracle.fsi_exact_int(v, d, l, nthreads=4)) < 1e-12, (d, l)
+            a = np.random.default_rng(5300 + 16 * d + l).standard_normal(1 << d)
+            plan = fsi.Plan(d, l, kernel="register", input="mobius")
+            got = plan.apply(torch.as_tensor(a).to(DEV)).cpu().numpy()
+            plan.close()
+            assert normwise(got, oracle.interaction_from_mobius_c(a, d, l, nthreads=4)) < 1e-12, (d, l)
+            g = games.tree_game(d, 30, 4, games.rng_for(5400, d))
+            v32 = games.tree_values(g).astype(np.float32)
+            plan = fsi.Plan(d, l, dtype="f32", kernel="register")
+            got = plan.apply(torch.from_numpy(v32).to(DEV)).double().cpu().numpy()
+            plan.close()
+            assert normwise(got, oracle.fsi(v32.astype(np.float64), d, l)) < 1e-6, (d, l)
 
 
 @pytest.mark.parametrize("d,l", [(24, 2), (25, 1)])
