@@ -107,6 +107,10 @@ constexpr int unit_index(int L, int sa, int sb) {
 // (two per instruction), and the two c-halves of a phase-B wave fall on
 // disjoint LDS banks
 constexpr int s2u(int L) { return (n3(L) + 7) & ~7; }
+// phase B writes the leaves of prefixes past the order to a padding unit
+// (n3 .. s2u - 1), which phase C never reads
+static_assert(s2u(1) > n3(1) && s2u(2) > n3(2) && s2u(3) > n3(3) && s2u(4) > n3(4),
+              "S2 needs a padding unit");
 constexpr int s2_elems(int L) { return (KAB + 1) * s2u(L) * NC; }
 
 // Phase-C thread map. Units in order of |sigma_AB| (stable). The heavy units

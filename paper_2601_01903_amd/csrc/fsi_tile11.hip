@@ -193,15 +193,22 @@ template <typename SwT, int L, int SAMIN, int SAMAX>
 struct EmitS2 {
   SwT* S2;   // offset by ((c / 4) * s2u + rankA) * 4 + c % 4
   int sA;    // in [SAMIN, SAMAX]
+  int rkA;   // rankA
   template <int SIG, int LO, int RC>
   __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
     constexpr int sB = cpop(SIG);
     if constexpr (sB <= L - SAMIN) {
-      if (sB <= L - SAMAX || sA <= L - sB) {
-        constexpr int UB = K<L>::ub.v[SIG];
-        constexpr int S2U = K<L>::S2U;
+      constexpr int UB = K<L>::ub.v[SIG];
+      constexpr int S2U = K<L>::S2U;
+      if constexpr (sB <= L - SAMAX) {
 #pragma unroll
         for (int i = 0; i < RC; ++i) S2[(2 * i * S2U + UB) * 4] = X[i][0];
+      } else {
+        // a prefix past the order writes a padding unit (n3 .. s2u - 1),
+        // which phase C never reads
+        const int ub = sA <= L - sB ? UB : K<L>::N3 - rkA;
+#pragma unroll
+        for (int i = 0; i < RC; ++i) S2[(2 * i * S2U + ub) * 4] = X[i][0];
       }
     }
   }
@@ -217,7 +224,7 @@ struct EmitZ {
   __device__ __forceinline__ void leaf(const SwT (&X)[RC][1]) {
     constexpr int sC = cpop(SIG);
     if constexpr (sC <= L - KMIN) {
-      if (sC <= L - KMAX || sAB <= L - sC) {
+      {   // leaves past the order write the dump row (zr)
         using V = typename Vec4<SwT>::type;
         constexpr int VN = Vec4<SwT>::n;
         V* p = reinterpret_cast<V*>(Z + zr[SIG] * ZROW);
@@ -450,7 +457,7 @@ __device__ __forceinline__ void phase_b(const SwT* S1, SwT* S2w, int sA, int p2r
     constexpr int R1 = row1_stride<SwT>();
     constexpr int NRB = PA + 1 - SAMIN;
     constexpr int W = HALF == 0 ? NB : H;       // inputs this half reads
-    EmitS2<SwT, L, SAMIN, SAMAX> e2{S2w, sA};
+    EmitS2<SwT, L, SAMIN, SAMAX> e2{S2w, sA, p2r};
     const SwT* src0 = S1 + p2r * R1 + NB * p2c + (HALF == 0 ? 0 : H);
     SwT X[NRB][W];
 #pragma unroll

@@ -253,9 +253,9 @@ def _ragged_refs(ds, ls, v32):
                                            ("f32_compensated", False), ("f32", False)])
 def test_ragged_batch_512_fp32(prec, autotune):
     """The 512-instance ragged batch (d ~ U{8..20}, l ~ U{1..4}, tree games),
-    FP32 storage, one graph replay, every instance against the oracle on the
-    same FP32 values: <= 1e-6 normwise; the default form both autotuned (the
-    launch the benchmark times) and with the default schedule."""
+    FP32 storage, one launch (graph replay), every instance against the oracle
+    on the same FP32 values: <= 1e-6 normwise; the default form both
+    autotuned (the launch the benchmark times) and with the default schedule."""
     fsi = fsi_mod()
     ds, ls, vals = _ragged_batch()
     say(f"[case] ragged batch n={len(ds)} {prec} autotune={autotune}, "
@@ -263,10 +263,20 @@ def test_ragged_batch_512_fp32(prec, autotune):
     v32 = [v.astype(np.float32) for v in vals]
     refs = _ragged_refs(ds, ls, v32)
     bp = fsi.BatchPlan(ds, ls, dtype="f32", precision=prec, autotune=autotune)
+    # every instance on the register-phase kernel: one tile kernel and one
+    # reduction
+    assert bp.schedule()["fast_instances"] == len(ds) and bp.num_stages() == 2
     flat = torch.from_numpy(np.concatenate(v32)).to(DEV)
     out = bp.apply(flat, graph=True)
     torch.cuda.synchronize()
     o = out.double().cpu().numpy()
+    # the stages launched one by one and further replays give the same bits
+    o2 = torch.empty_like(out)
+    bp.apply_stage(flat, o2, 0)
+    bp.apply_stage(flat, o2, 1)
+    out3 = bp.apply(flat, graph=True)
+    torch.cuda.synchronize()
+    assert torch.equal(o2, out) and torch.equal(out3, out)
     errs = []
     for i, (d, l) in enumerate(zip(ds, ls)):
         err = normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]], refs[i])
