@@ -428,6 +428,9 @@ def main():
         torch.cuda.synchronize()
         fms = ev0.elapsed_time(ev1) / args.steps
         forms[form] = {"ms_per_step": fms, "values_per_s": n * N / (fms * 1e-3),
+                       # whole step (tile kernel and reduction) against the
+                       # HBM peak, the same algorithmic bytes as the headline
+                       "hbm_frac_whole_step": n * N * 4 / (fms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                        "out": of.double().cpu().numpy()}
         bpf.close()
         log(f"precision form {form}: {fms:.3f} ms/step")

@@ -292,11 +292,15 @@ fsi_status fsi_apply_batched_noalloc(fsi_batch_plan_t plan,
 
 /* The kernel launches of one batched apply, for per-kernel timing. The
  * fused algorithm launches, in this order and each only if the plan has
- * such work: the register-phase tile kernel once per order l present
- * (in-tile Moebius + counter sweep + final weights + cross-tile sums per
- * work item), the generic tile kernel, the generic per-output reduction,
- * the wide gather and its final pass (generic instances with at least 2^10
- * tiles), and the reduction of the register-phase partial sums. The
+ * such work: the register-phase tile kernel once (in-tile Moebius + counter
+ * sweep + final weights + cross-tile sums per work item; one launch over
+ * the items of every order l present), the generic tile kernel, the generic
+ * per-output reduction, the wide gather and its final pass (generic
+ * instances with at least 2^10 tiles, register-phase instances of several
+ * blocks), and the reduction of the register-phase partial sums of
+ * one-block instances. A batch whose instances all take the register-phase
+ * kernel (l <= 4) and fit one block each (l <= 3, or d <= 20 at l = 4) has
+ * two stages. The
  * two-pass algorithm has 3 + (number of strided high-bit Moebius passes)
  * stages (low pass, high passes, tile kernel, reduction). Running stages
  * 0 .. n-1 in order on one stream equals fsi_apply_batched_nograph.
@@ -305,11 +309,11 @@ int fsi_batch_num_stages(fsi_batch_plan_t plan);
 fsi_status fsi_apply_batched_stage(fsi_batch_plan_t plan, const void* values_dev,
                                    void* out_dev, int stage, hipStream_t stream);
 
-/* Message for the last non-OK status returned on this thread ("" if none). */
 /* Schedule of a plan (host struct filled by the call). */
 fsi_status fsi_plan_schedule(fsi_plan_t plan, fsi_schedule* out);
 fsi_status fsi_batch_schedule(fsi_batch_plan_t plan, fsi_schedule* out);
 
+/* Message for the last non-OK status returned on this thread ("" if none). */
 const char* fsi_last_error(void);
 
 #ifdef __cplusplus
