@@ -228,8 +228,10 @@ struct EmitZ {
         using V = typename Vec4<SwT>::type;
         constexpr int VN = Vec4<SwT>::n;
         V* p = reinterpret_cast<V*>(Z + zr[SIG] * ZROW);
+        // the weight core reads a row's counters only (the first 12 - |S_L|
+        // entries, at most RC here): the padding past them is not stored
 #pragma unroll
-        for (int q = 0; q < ZROW / VN; ++q) {
+        for (int q = 0; q < (RC + VN - 1) / VN; ++q) {
           SwT e[VN];
 #pragma unroll
           for (int k = 0; k < VN; ++k) e[k] = q * VN + k < RC ? X[q * VN + k][0] : SwT(0);
@@ -364,8 +366,10 @@ __device__ __forceinline__ void lam_load(int lane, const SwT* Z, const double* l
       }
     }
     const V* zv = reinterpret_cast<const V*>(zr);
+    // a row task reads only its counters (12 - |S_L| entries)
+    constexpr int NV = T.kind == 0 ? (ZROW - T.S + VN - 1) / VN : ZROW / VN;
 #pragma unroll
-    for (int q = 0; q < ZROW / VN; ++q) {
+    for (int q = 0; q < NV; ++q) {
       const V v = zv[q];
       if constexpr (VN == 4) {
         zb[J * ZROW + 4 * q] = v.x; zb[J * ZROW + 4 * q + 1] = v.y;
