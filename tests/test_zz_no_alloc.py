@@ -2,9 +2,9 @@
 cannot allocate device memory at apply time): through the C ABI it must give
 the outputs of fsi_apply_batched_nograph on the same plan and input, on two
 calls in a row (the second plan smaller, so the static scratch array still
-holds the first call's words), for fused plans (register-phase and generic
-kernels) and a two-pass plan, and it must refuse a plan whose workspaces
-exceed the scratch array."""
+holds the first call's words), for fused plans (register-phase kernel with
+one-block, small-d and blocked instances, generic kernel) and a two-pass
+plan, and it must refuse a plan whose workspaces exceed the scratch array."""
 import ctypes
 
 import numpy as np
@@ -35,9 +35,9 @@ def _check_pair(bp, x, tag):
 
 
 def test_noalloc_matches_nograph_two_calls():
-    # call 1: a larger ragged FP32 batch (register-phase kernel at d >= 11,
-    # generic kernel at d = 9), call 2: a smaller one
-    ds1, ls1 = [20, 20, 16, 13, 9], [4, 2, 3, 4, 2]
+    # call 1: a larger ragged FP32 batch (register-phase kernel, d = 9 run as
+    # d = 11; generic kernel at l = 5), call 2: a smaller one
+    ds1, ls1 = [20, 20, 16, 13, 9, 12], [4, 2, 3, 4, 2, 5]
     bp1 = BatchPlan(ds1, ls1, dtype="f32")
     _check_pair(bp1, _values(ds1, 501, np.float32), "fp32 ragged, call 1")
     ds2, ls2 = [12, 8], [3, 2]
@@ -47,9 +47,14 @@ def test_noalloc_matches_nograph_two_calls():
     ds3, ls3 = [14, 10], [3, 2]
     bp3 = BatchPlan(ds3, ls3, dtype="f64", algo="two_pass")
     _check_pair(bp3, _values(ds3, 503, np.float64), "fp64 two-pass, call 3")
-    # and the first plan again after the smaller ones
-    _check_pair(bp1, _values(ds1, 504, np.float32), "fp32 ragged, call 4")
-    for bp in (bp1, bp2, bp3):
+    # a register-phase instance of several blocks (d = 21, l = 4: partial
+    # sums per block of 2^6 tiles, then the wide gather's partials)
+    ds4, ls4 = [21, 11], [4, 4]
+    bp4 = BatchPlan(ds4, ls4, dtype="f32")
+    _check_pair(bp4, _values(ds4, 505, np.float32), "fp32 blocked, call 4")
+    # and the first plan again after the others
+    _check_pair(bp1, _values(ds1, 504, np.float32), "fp32 ragged, call 5")
+    for bp in (bp1, bp2, bp3, bp4):
         bp.close()
 
 
