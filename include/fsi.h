@@ -250,7 +250,10 @@ fsi_status fsi_mobius(fsi_plan_t plan, void* a_dev, hipStream_t stream);
  * writes outputs [out_offset[i], out_offset[i+1]) of another; both offset
  * tables are prefix sums of 2^d_i and M(d_i, l_i) starting at 0. One apply
  * is a fixed sequence of persistent kernel launches over a device work list,
- * replayed from a captured HIP graph. */
+ * replayed from a captured HIP graph. The register-phase kernel's work items
+ * are sorted by decreasing cost; past the first round its workgroups take
+ * them from a queue in the plan's tables as they finish, and each launch
+ * leaves that queue as it found it (zero). */
 fsi_status fsi_plan_batched(int n, const int* d_host, const int* l_host,
                             const fsi_plan_opts* opts, fsi_batch_plan_t* out);
 fsi_status fsi_batch_plan_destroy(fsi_batch_plan_t plan);

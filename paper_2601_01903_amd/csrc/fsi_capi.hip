@@ -447,10 +447,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   }
   // several orders run as one launch over all items (the kernel dispatches
   // per item): the costliest items first (higher order, then more values),
-  // so the persistent grid ends evenly
+  // so that the launch's work queue ends evenly; one order: more values first
   int n_orders = 0;
   for (int l = 1; l <= kFastMaxL; ++l) n_orders += lbeg[l + 1] > lbeg[l];
-  if (n_orders > 1)
+  if (n_orders >= 1)
     std::stable_sort(fitems.begin(), fitems.end(), [&](const FastItem& x, const FastItem& y) {
       const int lx = item_l(x), ly = item_l(y);
       if (lx != ly) return lx > ly;
@@ -535,6 +535,10 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   size_t o_mob[kMaxMobPasses] = {0, 0, 0, 0};
   for (int p = 0; p < n_passes; ++p) o_mob[p] = stage(buf, mob[p].data(), mob[p].size());
   const size_t o_ooff = stage(buf, P->ooff.data(), P->ooff.size());
+  // work queue of the register-phase launches: zero here, and every launch
+  // leaves it zero
+  const uint32_t queue0[4] = {0u, 0u, 0u, 0u};
+  const size_t o_queue = stage(buf, queue0, 4);
 
   hipError_t e = hipMalloc(&P->arena, buf.size());
   if (e != hipSuccess) { return fail(FSI_ERR_OUT_OF_MEMORY, "hipMalloc(tables) failed"); }
@@ -670,6 +674,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     a.fast.items = reinterpret_cast<const FastItem*>(A + o_fitems);
     a.fast.torder = reinterpret_cast<const int32_t*>(A + o_torder);
     a.fast.partial = P->partial;
+    a.fast.queue = reinterpret_cast<uint32_t*>(A + o_queue);
     for (int l = 0; l <= kFastMaxL + 1; ++l) a.fast.lbeg[l] = lbeg[l];
     a.fast.mobius_in = 0;
     for (const FastClassHost& F : P->fclasses)

@@ -50,6 +50,9 @@ struct FastLaunch {
   const void* vals64;
   const int32_t* torder;
   double* partial;
+  // work queue of a launch: [0] next item, [1] workgroups done; zero before
+  // every launch (the last workgroup of a launch to finish resets both)
+  uint32_t* queue;
 };
 
 // lds[l]: dynamic LDS of the order-l kernel, 0 = not used by the plan.

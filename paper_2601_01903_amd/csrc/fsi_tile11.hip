@@ -847,6 +847,32 @@ __device__ __forceinline__ void run_item(const FastClassDev* __restrict__ C, con
     if (kk < nkk) P[kk * NT] = acc[kk];
 }
 
+// Work queue of a launch: workgroup b runs item b first, then takes the
+// next unclaimed item (from gridDim.x on) each time it is done, so items of
+// unequal cost (instances of different d and l in one batch) spread over the
+// machine as they finish (items are sorted by decreasing cost). queue[0]
+// counts the items taken after the first round, queue[1] the workgroups
+// that found the queue empty; the last of those clears both for the next
+// launch on the stream. A launch with no more items than workgroups does
+// not touch the queue.
+__device__ __forceinline__ int next_item(uint32_t* queue, int n_items) {
+  if (n_items <= (int)gridDim.x) return n_items;
+  __shared__ int s_item;
+  if (threadIdx.x == 0) s_item = (int)(gridDim.x + atomicAdd(queue, 1u));
+  __syncthreads();
+  return s_item;
+}
+__device__ __forceinline__ void queue_done(uint32_t* queue, int n_items) {
+  if (n_items > (int)gridDim.x && threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(queue + 1, 1u) == gridDim.x - 1) {
+      __threadfence();
+      atomicExch(queue, 0u);
+      atomicExch(queue + 1, 0u);
+    }
+  }
+}
+
 // One kernel per order l (the items of a launch all have that order).
 // FP32 sweep: two workgroups per CU (2 waves per SIMD), so at most 256 VGPRs
 // per thread; the FP64 sweep's LDS allows one workgroup per CU.
@@ -855,7 +881,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
               const FastItem* __restrict__ items, int n_items,
               const float* __restrict__ vals32, const double* __restrict__ vals64,
-              const int32_t* __restrict__ torder, double* __restrict__ partial) {
+              const int32_t* __restrict__ torder, double* __restrict__ partial,
+              uint32_t* __restrict__ queue) {
   extern __shared__ __align__(16) unsigned char smem[];
   {
     using LA = LdsAll<SwT, MobT>;
@@ -863,13 +890,14 @@ tile11_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restric
     if (threadIdx.x < LA::zeros / 4) z[threadIdx.x] = 0u;
     __syncthreads();
   }
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  for (int item = blockIdx.x; item < n_items; item = next_item(queue, n_items)) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
     run_item<L, SwT, MobT, IN64, MOBIN>(classes + I.fcls, I, W, vals32, vals64, torder, partial,
                                         smem);
     __syncthreads();
   }
+  queue_done(queue, n_items);
 }
 
 // Items of every order in one launch (a batch of instances with different
@@ -880,7 +908,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE)))
 tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __restrict__ insts,
                     const FastItem* __restrict__ items, int n_items,
                     const float* __restrict__ vals32, const double* __restrict__ vals64,
-                    const int32_t* __restrict__ torder, double* __restrict__ partial) {
+                    const int32_t* __restrict__ torder, double* __restrict__ partial,
+              uint32_t* __restrict__ queue) {
   extern __shared__ __align__(16) unsigned char smem[];
   {
     using LA = LdsAll<SwT, MobT>;
@@ -888,7 +917,7 @@ tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __r
     if (threadIdx.x < LA::zeros / 4) z[threadIdx.x] = 0u;
     __syncthreads();
   }
-  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+  for (int item = blockIdx.x; item < n_items; item = next_item(queue, n_items)) {
     const FastItem W = items[item];
     const InstDev I = insts[W.inst];
     const FastClassDev* C = classes + I.fcls;
@@ -901,6 +930,7 @@ tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __r
     }
     __syncthreads();
   }
+  queue_done(queue, n_items);
 }
 
 // Every order's kernel places the zero row past the regions of all orders
@@ -924,7 +954,7 @@ static hipError_t launch_t11_m(const FastLaunch& f, hipStream_t st) {
   auto k = t11::tile11_kernel<L, SwT, MobT, IN64, wpe_for<SwT>(), MOBIN>;
   hipLaunchKernelGGL(k, dim3(f.grid[L]), dim3(t11::NT), f.lds[L], st, f.classes, f.insts,
                      f.items + ib, n, static_cast<const float*>(f.vals32),
-                     static_cast<const double*>(f.vals64), f.torder, f.partial);
+                     static_cast<const double*>(f.vals64), f.torder, f.partial, f.queue);
   return hipGetLastError();
 }
 
@@ -954,7 +984,7 @@ static hipError_t launch_mixed_m(const FastLaunch& f, hipStream_t st) {
   auto k = t11::tile11_mixed_kernel<SwT, MobT, IN64, wpe_for<SwT>(), MOBIN>;
   hipLaunchKernelGGL(k, dim3(f.grid_mixed), dim3(t11::NT), f.lds_mixed, st, f.classes, f.insts,
                      f.items, f.n_items, static_cast<const float*>(f.vals32),
-                     static_cast<const double*>(f.vals64), f.torder, f.partial);
+                     static_cast<const double*>(f.vals64), f.torder, f.partial, f.queue);
   return hipGetLastError();
 }
 
