@@ -379,12 +379,17 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       ptot += (int64_t)F.nkk * kFastThreads;
     }
   }
-  // reduction of the register-phase partial sums of one-block instances: one
-  // output per thread when no instance has more than two items per output,
-  // else four item rows; instances of several blocks go to the wide gather
+  // reduction of the register-phase partial sums of one-block instances, in
+  // slot order (consecutive threads read consecutive slots of an item): one
+  // slot per thread when no instance has more than two items, four item rows
+  // up to 64 items, sixteen past that (a small instance split into one-tile
+  // items); instances of several blocks go to the wide gather
   int red_rows = 1;
   for (int i = 0; i < n; ++i)
-    if (insts[i].fast && insts[i].nitems > 2 && insts[i].nitems == insts[i].ipb) red_rows = 4;
+    if (insts[i].fast && insts[i].nitems == insts[i].ipb) {
+      if (insts[i].nitems > 64) red_rows = std::max(red_rows, 16);
+      else if (insts[i].nitems > 2) red_rows = std::max(red_rows, 4);
+    }
   const int red_width = kFastThreads / red_rows;
   std::vector<int2> red_chunks;
   int n_generic = 0;
@@ -399,8 +404,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       insts[i].wide = 1;
       continue;
     }
-    const int Mi = P->classes[P->cls_of[i]].M;
-    for (int k0 = 0; k0 < Mi; k0 += red_width) red_chunks.push_back(make_int2(i, k0));
+    const int nslot = insts[i].pstride;
+    for (int s0 = 0; s0 < nslot; s0 += red_width) red_chunks.push_back(make_int2(i, s0));
   }
   // wide gather items: per instance, output groups x ranges of tiles
   // (generic instances) or blocks (register-phase instances); the ranges (a
@@ -514,7 +519,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     co[c].osh = stage(buf, C.osh.data(), C.osh.size());
   }
   std::vector<FastClassDev> fdev(P->fclasses.size());
-  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm, osh2; };
+  struct FOffs { size_t lam, meta, gs8, unit_mask, zrow, pidx, uperm, osh2, sinv; };
   std::vector<FOffs> fo(P->fclasses.size());
   for (size_t f = 0; f < P->fclasses.size(); ++f) {
     const FastClassHost& F = P->fclasses[f];
@@ -523,6 +528,7 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     fo[f].gs8 = stage(buf, F.gs8.data(), F.gs8.size());
     fo[f].pidx = stage(buf, F.pidx.data(), F.pidx.size());
     fo[f].osh2 = stage(buf, F.osh2.data(), F.osh2.size());
+    fo[f].sinv = stage(buf, F.sinv.data(), F.sinv.size());
     fo[f].unit_mask = stage(buf, F.unit_mask.data(), F.unit_mask.size());
     fo[f].zrow = stage(buf, F.zrow.data(), F.zrow.size());
     fo[f].uperm = stage(buf, F.uperm.data(), F.uperm.size());
@@ -588,6 +594,9 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     if (insts[i].fast) {
       insts[i].pidx = reinterpret_cast<const int32_t*>(A + fo[insts[i].fcls].pidx);
       insts[i].osh2 = reinterpret_cast<const uint32_t*>(A + fo[insts[i].fcls].osh2);
+      insts[i].sinv = P->fclasses[insts[i].fcls].sinv.empty()
+                          ? nullptr
+                          : reinterpret_cast<const int32_t*>(A + fo[insts[i].fcls].sinv);
     }
   // instance descriptors carry the fast fields filled above
   std::memcpy(buf.data() + o_inst, insts.data(), insts.size() * sizeof(InstDev));

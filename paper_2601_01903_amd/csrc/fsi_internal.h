@@ -71,6 +71,9 @@ struct FastClassHost {
   // sum for j2 = 0 .. l (whole instances: every entry the j2 = 0 slot)
   std::vector<int32_t> pidx;
   std::vector<uint32_t> osh2;   // [M] S_H2 = S_H >> kb of canonical output k
+  // [nkk * 256] canonical output of slot kk * 256 + t for one-block classes
+  // (its j2 = 0 slot), -1 for an unused slot; empty for blocked classes
+  std::vector<int32_t> sinv;
 };
 
 struct InstDev {
@@ -95,6 +98,8 @@ struct InstDev {
   int32_t pad2;
   const int32_t* pidx;   // [M * pw] position of canonical output k's partial sum for j2
   const uint32_t* osh2;  // [M] S_H2 of canonical output k
+  const int32_t* sinv;   // [pstride] canonical output whose partial sum a slot holds
+                         // (one-block instances), -1 for an unused slot
 };
 
 // Host-side tables of one class (built once, uploaded into a device arena).

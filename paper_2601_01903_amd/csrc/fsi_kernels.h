@@ -116,9 +116,9 @@ struct LaunchArgs {
   const WideGroup* wide_groups;
   int n_wide_groups, grid_wide_groups;
   double* wide_partial;
-  const int2* red_chunks;     // (instance, first output) per 256 / red_rows outputs of fast instances
+  const int2* red_chunks;     // (instance, first slot) per 256 / red_rows slots of fast instances
   int n_red_chunks, grid_red_chunks;
-  int red_rows;               // 1 or 4: item sums per output in the reduction
+  int red_rows;               // 1, 4 or 16: item rows per slot in the reduction
 };
 
 // Sets the dynamic-LDS limits of the kernels a plan will launch (call once

@@ -358,36 +358,39 @@ wide_final_kernel(const WideGroup* __restrict__ groups, int n_groups,
   }
 }
 
-// Sum of the register-phase kernel's per-item partial results. A workgroup
-// owns 256 / ROWS outputs of one instance; thread (o, r) adds the items
-// j = r mod ROWS in increasing order, then the ROWS sums are combined in a
-// fixed order, so the result is bitwise repeatable. ROWS = 1 when every
-// instance has at most two items per output (the usual batched case: one
-// output per thread, no LDS step), else 4.
+// Sum of the register-phase kernel's per-item partial results, in slot
+// order: a workgroup owns 256 / ROWS consecutive slots of one instance (so
+// a row of threads reads consecutive words of an item's partial sums), and
+// writes each slot's sum to the output the slot holds (none for an unused
+// slot). Thread (o, r) adds the items j = r mod ROWS in increasing order,
+// then the ROWS sums are combined in a fixed order, so the result is bitwise
+// repeatable (and, for at most ROWS items, the plain sum in item order).
+// ROWS = 1 when every instance has at most two items (the usual batched
+// case: one slot per thread, no LDS step), 4 up to 64 items, else 16.
 template <typename OutT, int ROWS>
 __global__ void __launch_bounds__(256)
 fast_reduce_kernel(const InstDev* __restrict__ insts, const int2* __restrict__ chunks,
-                   int n_chunks, const int64_t* __restrict__ out_offset,
-                   const double* __restrict__ partial, OutT* __restrict__ out) {
+                   int n_chunks, const double* __restrict__ partial, OutT* __restrict__ out) {
   constexpr int W = 256 / ROWS;
   __shared__ double part[ROWS][W];
   const int o = threadIdx.x % W, r = threadIdx.x / W;
   for (int ch = blockIdx.x; ch < n_chunks; ch += gridDim.x) {
     const int2 c = chunks[ch];
     const InstDev I = insts[c.x];
-    const int M = (int)(out_offset[c.x + 1] - out_offset[c.x]);
-    const int k = c.y + o;
+    const int s = c.y + o;
+    const int k = s < I.pstride ? I.sinv[s] : -1;
     double acc = 0.0;
-    if (k < M) {
-      const double* P = partial + I.pbase + I.pidx[(int64_t)k * I.pw];
+    if (k >= 0) {
+      const double* P = partial + I.pbase + s;
+#pragma unroll 4
       for (int j = r; j < I.nitems; j += ROWS) acc += P[(int64_t)j * I.pstride];
     }
     if constexpr (ROWS == 1) {
-      if (k < M) out[I.ooff + k] = (OutT)acc;
+      if (k >= 0) out[I.ooff + k] = (OutT)acc;
     } else {
       part[r][o] = acc;
       __syncthreads();
-      if (r == 0 && k < M) {
+      if (r == 0 && k >= 0) {
         double t = part[0][o];
 #pragma unroll
         for (int q = 1; q < ROWS; ++q) t += part[q][o];
@@ -534,11 +537,15 @@ hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t st) {
   if (a.algo == ALGO_FUSED && a.n_red_chunks > 0 && stage == last) {
     if (a.red_rows == 1)
       hipLaunchKernelGGL((fast_reduce_kernel<InT, 1>), dim3(a.grid_red_chunks), dim3(256), 0, st,
-                         a.insts, a.red_chunks, a.n_red_chunks, a.out_offset, a.partial,
+                         a.insts, a.red_chunks, a.n_red_chunks, a.partial,
+                         static_cast<InT*>(a.out));
+    else if (a.red_rows == 4)
+      hipLaunchKernelGGL((fast_reduce_kernel<InT, 4>), dim3(a.grid_red_chunks), dim3(256), 0, st,
+                         a.insts, a.red_chunks, a.n_red_chunks, a.partial,
                          static_cast<InT*>(a.out));
     else
-      hipLaunchKernelGGL((fast_reduce_kernel<InT, 4>), dim3(a.grid_red_chunks), dim3(256), 0, st,
-                         a.insts, a.red_chunks, a.n_red_chunks, a.out_offset, a.partial,
+      hipLaunchKernelGGL((fast_reduce_kernel<InT, 16>), dim3(a.grid_red_chunks), dim3(256), 0, st,
+                         a.insts, a.red_chunks, a.n_red_chunks, a.partial,
                          static_cast<InT*>(a.out));
     return hipGetLastError();
   }

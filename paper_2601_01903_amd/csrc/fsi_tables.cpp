@@ -436,6 +436,15 @@ std::string build_fast_class(const ClassHost& C, FastClassHost* F) {
       F->pidx[k * (size_t)(l + 1) + j2] = it->second;
     }
   }
+  if (!blocked) {
+    F->sinv.assign((size_t)F->nkk * kFastThreads, -1);
+    for (size_t k = 0; k < M; ++k) {
+      const int32_t slot = F->pidx[k * (size_t)(l + 1)];
+      if (slot < 0 || (size_t)slot >= F->sinv.size() || F->sinv[slot] != -1)
+        return "output slots are not one to one";
+      F->sinv[slot] = (int32_t)k;
+    }
+  }
   return "";
 }
 
