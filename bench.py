@@ -536,6 +536,30 @@ def main():
                     pl3.close()
         log("d=20 single instances at l = 2, 4 computed")
 
+    # ---- latency of one instance (fsi_apply: direct launches, default
+    # schedule), FP32 storage, the headline's first instance ----
+    single = None
+    if not args.no_c3:
+        single = {}
+        xs = x32[:N]
+        for l1 in (2, 4):
+            p1 = Plan(d, l1, dtype="f32", precision=args.precision)
+            o1 = p1.apply(xs)
+            for _ in range(5):
+                p1.apply(xs, o1)
+            torch.cuda.synchronize()
+            reps = 50
+            ev0.record(stream)
+            for _ in range(reps):
+                p1.apply(xs, o1)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            us = ev0.elapsed_time(ev1) / reps * 1e3
+            single[f"d{d}_l{l1}"] = {"us_per_apply": us, "values_per_s": N / (us * 1e-6),
+                                     "schedule": p1.schedule()}
+            p1.close()
+        log(f"single-instance latency: {single}")
+
     # ---- FP64 paths on the same instances ----
     fp64 = None
     errs = None
@@ -762,6 +786,7 @@ def main():
         "indices": indices,
         "value_function": vfun,
         "large_instances": large,
+        "single_instance": single,
         "ragged": ragged,
         "single_d20": c3,
         "cpu_baseline": cpu,
