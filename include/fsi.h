@@ -79,6 +79,10 @@ typedef enum {
 } fsi_precision;
 
 typedef enum {
+  /* The fused algorithm, except for plans whose instances all have l >= 7
+   * (value input): there the two-pass one, whose sweep does not grow with
+   * the number of outputs the way the fused gather does. With the
+   * autotuner, a plan whose instances all have l > 4 times both. */
   FSI_ALGO_AUTO = 0,
   /* One read of v: per tile of the low b bits, the in-tile Moebius and the
    * counter sweep; the high-site Moebius cores are precontracted into the
@@ -176,7 +180,9 @@ typedef struct fsi_batch_plan_s* fsi_batch_plan_t;
  * algorithm the register-phase kernel at 1/2x, 1x, 2x and 4x the default
  * tiles per work item and the generic kernel at the largest tile that fits
  * LDS and 1 or 2 bits less; for the two-pass algorithm 4, 5 or 6 bits per
- * strided high Moebius pass, with the largest tile or 1 bit less. The
+ * strided high Moebius pass, with the largest tile or 1 bit less;
+ * FSI_ALGO_AUTO takes the candidates of both algorithms when every instance
+ * has l > 4, else those of the algorithm it resolves to. The
  * choice is cached per (device architecture and compute-unit count, dtype,
  * precision, algo, kernel, tile_bits, input, multiset of (d, l)) in the
  * process and in a JSON file read by later processes: the path in the
@@ -190,7 +196,8 @@ typedef struct {
   int32_t fast_instances;   /* instances on the register-phase kernel       */
   int32_t tiles_per_item;   /* register-phase kernel: tiles per work item   */
   int32_t tile_shift;       /* generic tile: bits below the largest fitting */
-  int32_t mob_group;        /* two-pass: bits per strided high pass, else 0 */
+  int32_t mob_group;        /* two-pass: bits per strided high pass; 0 for  */
+                            /* the fused algorithm                          */
   float tuned_ms;           /* measured time of the chosen schedule (ms)    */
 } fsi_schedule;
 

@@ -179,7 +179,23 @@ struct Sched {
   int tb_shift = 0;     // generic tile: bits relative to the largest that fits LDS (<= 0)
   int chunk_shift = 0;  // register-phase kernel: log2 tiles per item relative to the default
   int mob_group = 0;    // two-pass: bits per strided high Moebius pass (0: 6)
+  int algo = 0;         // FSI_ALGO_FUSED or FSI_ALGO_TWO_PASS; 0: the option's
 };
+
+// FSI_ALGO_AUTO without the autotuner: the fused algorithm, unless every
+// instance has an order of at least kAutoTwoPassL (value input). Such
+// instances run on the generic kernel, whose per-tile results feed a gather
+// over M outputs x 2^h tiles; the two-pass algorithm's counter sweep over
+// the Moebius transform does not grow that way with M (32 x d = 20 at
+// l = 8: 7.6 against 29 ms in FP32, 16 against 32 ms in FP64; at l = 6 the
+// two are within 15% either way, at l = 5 the fused one is faster).
+constexpr int kAutoTwoPassL = 7;
+int auto_algo(int n, const int* lh, const fsi_plan_opts& o) {
+  if (o.input != FSI_INPUT_VALUES) return ALGO_FUSED;
+  for (int i = 0; i < n; ++i)
+    if (lh[i] < kAutoTwoPassL) return ALGO_FUSED;
+  return ALGO_TWO_PASS;
+}
 
 fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts* opts_in,
                        bool single, fsi_batch_plan_s** out, const Sched& sc = Sched{}) {
@@ -210,7 +226,12 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     return fail(FSI_ERR_INVALID_ARG, "FP32 storage needs an FP32 precision mode");
   if (opts.algo < 0 || opts.algo > FSI_ALGO_TWO_PASS)
     return fail(FSI_ERR_INVALID_ARG, "unknown algo");
-  const int algo = opts.algo == FSI_ALGO_AUTO ? ALGO_FUSED : opts.algo;
+  // FSI_ALGO_AUTO: the autotuner's choice (a schedule's algorithm), else the
+  // heuristic; an explicit algorithm is never overridden
+  const bool sched_algo = opts.algo == FSI_ALGO_AUTO && opts.input == FSI_INPUT_VALUES &&
+                          (sc.algo == FSI_ALGO_FUSED || sc.algo == FSI_ALGO_TWO_PASS);
+  const int algo = sched_algo ? sc.algo
+                   : opts.algo == FSI_ALGO_AUTO ? auto_algo(n, lh, opts) : opts.algo;
   if (opts.block_threads != 0)
     return fail(FSI_ERR_INVALID_ARG, "block_threads is reserved and must be 0");
   if (opts.tile_bits < 0 || opts.tile_bits > kMaxTileBits)
@@ -751,7 +772,8 @@ std::string tune_file_path() {
 }
 
 // One entry per line:
-//   {"key": "...", "kernel": K, "tb_shift": T, "chunk_shift": C, "mob_group": G},
+//   {"key": "...", "kernel": K, "tb_shift": T, "chunk_shift": C, "mob_group": G, "algo": A},
+// (entries without "algo" read as A = 0, the option's algorithm)
 // inside {"format": "fsi-autotune-1", "entries": [ ... ]}. Keys hold only
 // [0-9a-z/;,x-], so no escapes are needed; lines that do not parse are
 // skipped.
@@ -768,9 +790,12 @@ void tune_file_load(std::map<std::string, Sched>& m) {
     const char* ke = std::strchr(k, '"');
     if (!ke) continue;
     Sched sc;
-    if (std::sscanf(ke + 1, ", \"kernel\": %d, \"tb_shift\": %d, \"chunk_shift\": %d, \"mob_group\": %d",
-                    &sc.kernel, &sc.tb_shift, &sc.chunk_shift, &sc.mob_group) != 4)
-      continue;
+    const int got = std::sscanf(
+        ke + 1, ", \"kernel\": %d, \"tb_shift\": %d, \"chunk_shift\": %d, \"mob_group\": %d, \"algo\": %d",
+        &sc.kernel, &sc.tb_shift, &sc.chunk_shift, &sc.mob_group, &sc.algo);
+    if (got != 4 && got != 5) continue;
+    if (got == 4) sc.algo = 0;
+    if (sc.algo != 0 && sc.algo != FSI_ALGO_FUSED && sc.algo != FSI_ALGO_TWO_PASS) continue;
     m.emplace(std::string(k, ke), sc);
   }
   std::fclose(f);
@@ -790,9 +815,9 @@ void tune_file_save(const std::map<std::string, Sched>& m) {
   for (const auto& e : m) {
     ok = ok && std::fprintf(f,
                             "{\"key\": \"%s\", \"kernel\": %d, \"tb_shift\": %d, "
-                            "\"chunk_shift\": %d, \"mob_group\": %d}%s\n",
+                            "\"chunk_shift\": %d, \"mob_group\": %d, \"algo\": %d}%s\n",
                             e.first.c_str(), e.second.kernel, e.second.tb_shift,
-                            e.second.chunk_shift, e.second.mob_group,
+                            e.second.chunk_shift, e.second.mob_group, e.second.algo,
                             ++i < m.size() ? "," : "") > 0;
   }
   ok = ok && std::fprintf(f, "]}\n") > 0;
@@ -874,18 +899,32 @@ fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts*
   }
   // candidates
   std::vector<Sched> cand;
-  const bool fused = opts.algo != FSI_ALGO_TWO_PASS;
+  // FSI_ALGO_AUTO times both algorithms when no instance can take the
+  // register-phase kernel (every order above 4, value input); otherwise the
+  // fused algorithm, as without the autotuner
+  bool all_generic = opts.input == FSI_INPUT_VALUES && opts.kernel != FSI_KERNEL_REGISTER;
+  for (int i = 0; i < n && all_generic; ++i) all_generic = lh[i] > kFastMaxL;
+  const bool both = opts.algo == FSI_ALGO_AUTO && all_generic;
+  const int fused_algo = both ? FSI_ALGO_FUSED : 0;
+  const bool fused = opts.algo == FSI_ALGO_FUSED || (opts.algo == FSI_ALGO_AUTO &&
+                                                     (both || auto_algo(n, lh, opts) == ALGO_FUSED));
+  const bool two_pass = opts.algo == FSI_ALGO_TWO_PASS || both ||
+                        (opts.algo == FSI_ALGO_AUTO && auto_algo(n, lh, opts) == ALGO_TWO_PASS);
   if (fused) {
     if (opts.kernel != FSI_KERNEL_GENERIC)
-      for (int cs = -1; cs <= 2; ++cs) { Sched s; s.kernel = opts.kernel; s.chunk_shift = cs; cand.push_back(s); }
+      for (int cs = -1; cs <= 2; ++cs) {
+        Sched s; s.kernel = opts.kernel; s.chunk_shift = cs; s.algo = fused_algo; cand.push_back(s);
+      }
     if (opts.kernel != FSI_KERNEL_REGISTER)
       for (int tb = 0; tb >= (opts.tile_bits ? 0 : -2); --tb) {
-        Sched s; s.kernel = FSI_KERNEL_GENERIC; s.tb_shift = tb; cand.push_back(s);
+        Sched s; s.kernel = FSI_KERNEL_GENERIC; s.tb_shift = tb; s.algo = fused_algo; cand.push_back(s);
       }
-  } else {
+  }
+  if (two_pass) {
     for (int g = 4; g <= 6; ++g)
       for (int tb = 0; tb >= (opts.tile_bits ? 0 : -1); --tb) {
-        Sched s; s.mob_group = g; s.tb_shift = tb; cand.push_back(s);
+        Sched s; s.mob_group = g; s.tb_shift = tb; s.algo = both ? FSI_ALGO_TWO_PASS : 0;
+        cand.push_back(s);
       }
   }
   fsi_batch_plan_s* best = nullptr;

@@ -476,3 +476,35 @@ def test_autotuned_plans_match_oracle():
             assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]],
                             oracle.fsi_exact_int(v, d, l, nthreads=8)) < INT_TOL[algo], (algo, i)
         bp.close()
+
+
+def test_auto_algorithm_for_high_orders():
+    """FSI_ALGO_AUTO runs the two-pass algorithm when every instance has
+    l >= 7, the fused one otherwise (the schedule reports mob_group > 0 for
+    two-pass); with the autotuner and every l > 4 it times both. Every
+    result is within 1e-12 of the exact-integer oracle."""
+    fsi = fsi_mod()
+    cases = [([12, 10, 11], [7, 9, 8], True), ([12, 10, 11], [7, 5, 8], False),
+             ([12, 13], [4, 7], False)]
+    for ds, ls, two_pass in cases:
+        say(f"[case] auto algorithm ds={ds} ls={ls}")
+        vals = _batch_inputs(ds, 9100)
+        bp = fsi.BatchPlan(ds, ls, dtype="f64")
+        assert (bp.schedule()["mob_group"] > 0) == two_pass, bp.schedule()
+        o = bp.apply(torch.from_numpy(np.concatenate(vals)).to(DEV)).cpu().numpy()
+        for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
+            assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]],
+                            oracle.fsi_exact_int(v, d, l, nthreads=8)) < 1e-12, (ds, ls, i)
+        bp.close()
+    ds, ls = [12, 11], [6, 8]
+    say(f"[case] auto algorithm, autotuned, ds={ds} ls={ls}")
+    vals = _batch_inputs(ds, 9200)
+    bp = fsi.BatchPlan(ds, ls, dtype="f64", autotune=True)
+    sc = bp.schedule()
+    say(f"  schedule {sc}")
+    assert sc["autotuned"] == 1
+    o = bp.apply(torch.from_numpy(np.concatenate(vals)).to(DEV)).cpu().numpy()
+    for i, (v, d, l) in enumerate(zip(vals, ds, ls)):
+        assert normwise(o[bp.out_offset[i]:bp.out_offset[i + 1]],
+                        oracle.fsi_exact_int(v, d, l, nthreads=8)) < 1e-12, (i, d, l)
+    bp.close()
