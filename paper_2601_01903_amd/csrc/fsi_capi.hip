@@ -457,8 +457,8 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
       }
     }
   }
-  // one launch per order l: items grouped by l (stable, so each group keeps
-  // the instance order)
+  // the items of each order l counted (a plan with one order launches the
+  // kernel compiled for it)
   auto item_l = [&](const FastItem& it) { return P->fclasses[P->fast_of[P->cls_of[it.inst]]].l; };
   std::stable_sort(fitems.begin(), fitems.end(),
                    [&](const FastItem& x, const FastItem& y) { return item_l(x) < item_l(y); });

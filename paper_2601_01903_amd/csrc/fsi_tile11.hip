@@ -909,7 +909,7 @@ tile11_mixed_kernel(const FastClassDev* __restrict__ classes, const InstDev* __r
                     const FastItem* __restrict__ items, int n_items,
                     const float* __restrict__ vals32, const double* __restrict__ vals64,
                     const int32_t* __restrict__ torder, double* __restrict__ partial,
-              uint32_t* __restrict__ queue) {
+                    uint32_t* __restrict__ queue) {
   extern __shared__ __align__(16) unsigned char smem[];
   {
     using LA = LdsAll<SwT, MobT>;
