@@ -80,9 +80,10 @@ typedef enum {
 
 typedef enum {
   /* The fused algorithm, except for plans whose instances all have l >= 7
-   * (value input): there the two-pass one, whose sweep does not grow with
-   * the number of outputs the way the fused gather does. With the
-   * autotuner, a plan whose instances all have l > 4 times both. */
+   * (value input, kernel FSI_KERNEL_AUTO): there the two-pass one, whose
+   * sweep does not grow with the number of outputs the way the fused gather
+   * does. With the autotuner, such a plan whose instances all have l > 4
+   * times both. */
   FSI_ALGO_AUTO = 0,
   /* One read of v: per tile of the low b bits, the in-tile Moebius and the
    * counter sweep; the high-site Moebius cores are precontracted into the

@@ -183,7 +183,8 @@ struct Sched {
 };
 
 // FSI_ALGO_AUTO without the autotuner: the fused algorithm, unless every
-// instance has an order of at least kAutoTwoPassL (value input). Such
+// instance has an order of at least kAutoTwoPassL (value input, no kernel
+// named: a named kernel is one of the fused algorithm's). Such
 // instances run on the generic kernel, whose per-tile results feed a gather
 // over M outputs x 2^h tiles; the two-pass algorithm's counter sweep over
 // the Moebius transform does not grow that way with M (32 x d = 20 at
@@ -191,7 +192,7 @@ struct Sched {
 // two are within 15% either way, at l = 5 the fused one is faster).
 constexpr int kAutoTwoPassL = 7;
 int auto_algo(int n, const int* lh, const fsi_plan_opts& o) {
-  if (o.input != FSI_INPUT_VALUES) return ALGO_FUSED;
+  if (o.input != FSI_INPUT_VALUES || o.kernel != FSI_KERNEL_AUTO) return ALGO_FUSED;
   for (int i = 0; i < n; ++i)
     if (lh[i] < kAutoTwoPassL) return ALGO_FUSED;
   return ALGO_TWO_PASS;
@@ -900,9 +901,9 @@ fsi_status build_tuned(int n, const int* dh, const int* lh, const fsi_plan_opts*
   // candidates
   std::vector<Sched> cand;
   // FSI_ALGO_AUTO times both algorithms when no instance can take the
-  // register-phase kernel (every order above 4, value input); otherwise the
-  // fused algorithm, as without the autotuner
-  bool all_generic = opts.input == FSI_INPUT_VALUES && opts.kernel != FSI_KERNEL_REGISTER;
+  // register-phase kernel (every order above 4, value input, no kernel
+  // named); otherwise the algorithm it resolves to without the autotuner
+  bool all_generic = opts.input == FSI_INPUT_VALUES && opts.kernel == FSI_KERNEL_AUTO;
   for (int i = 0; i < n && all_generic; ++i) all_generic = lh[i] > kFastMaxL;
   const bool both = opts.algo == FSI_ALGO_AUTO && all_generic;
   const int fused_algo = both ? FSI_ALGO_FUSED : 0;
