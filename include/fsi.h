@@ -158,12 +158,14 @@ typedef struct {
 
 /* Tile kernel of the fused algorithm. The register-phase kernel (tiles of
  * 11 low bits) covers every storage dtype and precision except
- * F32_FP64REG, at l <= 4 for 11 <= d <= 30 (past d = 20 at l = 4 the outputs
- * outnumber a workgroup's accumulators: a work item then covers a block of
- * 2^6 tiles sharing their top high bits, and the wide gather combines the
- * blocks' partial sums; every tile is still read and swept once); the
- * generic LDS kernel covers every (d, l). AUTO picks the register-phase
- * kernel where it applies. */
+ * F32_FP64REG, at l <= 4 for every d <= 30: an instance with d < 11 runs as
+ * the d = 11 instance of the game that ignores the players past d (its
+ * scores on the first d players are the same, the weights not depending on
+ * d), and past d = 20 at l = 4 the outputs outnumber a workgroup's
+ * accumulators: a work item then covers a block of 2^6 tiles sharing their
+ * top high bits, and the wide gather combines the blocks' partial sums;
+ * every tile is still read and swept once. The generic LDS kernel covers
+ * every (d, l). AUTO picks the register-phase kernel where it applies. */
 typedef enum {
   FSI_KERNEL_AUTO = 0,
   FSI_KERNEL_GENERIC = 1,
