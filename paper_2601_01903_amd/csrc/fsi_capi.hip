@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <functional>
+#include <queue>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -365,20 +367,89 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
   int64_t fast_tiles = 0;
   for (int i = 0; i < n; ++i)
     if (P->fast_of[P->cls_of[i]] >= 0) fast_tiles += (int64_t)1 << P->classes[P->cls_of[i]].h;
-  // tiles per work item: the largest power of two that still gives every
-  // workgroup slot of the machine at least one item
+  // tiles per work item: the candidate size (powers of two and 1.5 times
+  // them) whose simulated launch ends first. The model: an item costs its
+  // tiles at the order's measured cost per tile plus a fixed cost (the first
+  // tile's loads, which nothing prefetches, and the partial-sum write);
+  // workgroup b runs item b, then the workgroups take the items in order of
+  // decreasing cost as they finish (the kernel's work queue); the reduction
+  // reads every item's partial sums. Small items balance the end of the
+  // launch, large ones write fewer partial sums.
+  int slots = n_cu;
+  for (size_t f = 0; f < P->fclasses.size(); ++f)
+    slots = std::max(slots, n_cu * fast_wgs_per_cu(prec, P->fclasses[f].l));
+  // tiles of one item of instance i at a nominal size c: any size inside a
+  // one-block instance (its last item takes the rest), a power of two
+  // dividing the block for an instance of several blocks
+  auto item_tiles = [&](int i, int64_t c) {
+    const FastClassHost& F = P->fclasses[P->fast_of[P->cls_of[i]]];
+    const int64_t ntile = (int64_t)1 << F.h, bsize = (int64_t)1 << F.kb;
+    if (F.kb >= F.h) return std::min<int64_t>(c, ntile);
+    int64_t cs = std::min<int64_t>(c, bsize);
+    while (cs & (cs - 1)) cs &= cs - 1;
+    return cs;
+  };
   int64_t chunk = 1;
   {
-    int slots = n_cu;
-    for (size_t f = 0; f < P->fclasses.size(); ++f)
-      slots = std::max(slots, n_cu * fast_wgs_per_cu(prec, P->fclasses[f].l));
-    while (chunk * 2 * slots <= fast_tiles) chunk *= 2;
+    static const double kTileUs[kFastMaxL + 1] = {0.0, 2.47, 3.03, 3.65, 3.79};
+    const double tile_scale = prec == PREC_F64 ? 2.3 : 1.0;
+    const double item_us = 6.0, red_base_us = 4.0, red_bytes_per_us = 3.0e6;
+    int64_t max_tiles = 1;
+    for (int i = 0; i < n; ++i)
+      if (P->fast_of[P->cls_of[i]] >= 0)
+        max_tiles = std::max<int64_t>(max_tiles, (int64_t)1 << P->classes[P->cls_of[i]].h);
+    std::vector<int64_t> cand;
+    for (int64_t c2 = 1; c2 <= max_tiles; c2 *= 2) {
+      cand.push_back(c2);
+      if (c2 >= 2 && c2 + c2 / 2 <= max_tiles) cand.push_back(c2 + c2 / 2);
+    }
+    double best = -1.0;
+    std::vector<double> cost;
+    for (int64_t c : cand) {
+      // sizes that cut the batch into far more items than workgroups only
+      // add partial sums (the largest size is always simulated)
+      int64_t items = 0;
+      for (int i = 0; i < n; ++i)
+        if (P->fast_of[P->cls_of[i]] >= 0) {
+          const int64_t ntile = (int64_t)1 << P->classes[P->cls_of[i]].h;
+          items += (ntile + item_tiles(i, c) - 1) / item_tiles(i, c);
+        }
+      if (items > 64 * (int64_t)slots && c != cand.back()) continue;
+      cost.clear();
+      double part_bytes = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const int f = P->fast_of[P->cls_of[i]];
+        if (f < 0) continue;
+        const FastClassHost& F = P->fclasses[f];
+        const int64_t ntile = (int64_t)1 << F.h, cs = item_tiles(i, c);
+        for (int64_t tb = 0; tb < ntile; tb += cs) {
+          const int64_t nt = std::min<int64_t>(cs, ntile - tb);
+          cost.push_back((double)nt * kTileUs[F.l] * tile_scale + item_us);
+          part_bytes += (double)F.nkk * kFastThreads * 8.0;
+        }
+      }
+      std::sort(cost.begin(), cost.end(), std::greater<double>());
+      std::priority_queue<double, std::vector<double>, std::greater<double>> busy;
+      for (double x : cost) {
+        if ((int)busy.size() < slots) {
+          busy.push(x);
+        } else {
+          const double t = busy.top();
+          busy.pop();
+          busy.push(t + x);
+        }
+      }
+      double end = 0.0;
+      while (!busy.empty()) { end = std::max(end, busy.top()); busy.pop(); }
+      const double total = end + red_base_us + part_bytes / red_bytes_per_us;
+      if (best < 0.0 || total < best) { best = total; chunk = c; }
+    }
     if (sc.chunk_shift > 0) chunk <<= sc.chunk_shift;
     if (sc.chunk_shift < 0) chunk = std::max<int64_t>(1, chunk >> -sc.chunk_shift);
   }
-  // work items: tile ranges of 2^c tiles inside a block (c <= kb), block
-  // by block; item j of an instance covers block j / ipb and has its partial
-  // sums at pbase + j * pstride
+  // work items: tile ranges of an instance's tile order (inside a block for
+  // instances of several blocks); item j of an instance covers block j / ipb
+  // and has its partial sums at pbase + j * pstride
   std::vector<FastItem> fitems;
   int64_t ptot = 0;
   for (int i = 0; i < n; ++i) {
@@ -386,18 +457,19 @@ fsi_status build_batch(int n, const int* dh, const int* lh, const fsi_plan_opts*
     if (f < 0) continue;
     const FastClassHost& F = P->fclasses[f];
     const int64_t ntile = (int64_t)1 << F.h, bsize = (int64_t)1 << F.kb;
-    const int64_t cs = std::min<int64_t>(chunk, bsize);
+    const int64_t cs = item_tiles(i, chunk);
+    const int64_t nit = (ntile + cs - 1) / cs;
     insts[i].fast = 1;
     insts[i].fcls = f;
     insts[i].tofs = tofs_of_fast[f];
     insts[i].pbase = ptot;
     insts[i].pstride = F.nkk * kFastThreads;
-    insts[i].nitems = (int32_t)(ntile / cs);
-    insts[i].ipb = (int32_t)(bsize / cs);
+    insts[i].nitems = (int32_t)nit;
+    insts[i].ipb = (int32_t)(F.kb >= F.h ? nit : bsize / cs);
     insts[i].pw = F.l + 1;
     insts[i].lowmask = dh[i] < kFastTileBits ? (1 << dh[i]) - 1 : (1 << kFastTileBits) - 1;
     for (int64_t tb = 0; tb < ntile; tb += cs) {
-      fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)(tb + cs), 0, ptot});
+      fitems.push_back(FastItem{i, (int32_t)tb, (int32_t)std::min<int64_t>(tb + cs, ntile), 0, ptot});
       ptot += (int64_t)F.nkk * kFastThreads;
     }
   }

@@ -20,12 +20,13 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
 
-# one order (l = 3, d from 9 to 20) and four orders on the same shapes: 1456
-# tiles, a few tiles per item at the default schedule, over at most 512
-# workgroups
+# one order (l = 3, d from 9 to 20) and four orders on the same shapes:
+# 8624 tiles, cut by the default schedule into more work items than the 512
+# workgroups of the grid (asserted below)
+_DS = [20] * 16 + [12, 19, 11, 16, 14, 9, 18, 13]
 CASES = {
-    "one_order": ([20, 12, 19, 11, 16, 20, 14, 9, 18, 13], [3] * 10),
-    "four_orders": ([20, 12, 19, 11, 16, 20, 14, 9, 18, 13], [4, 1, 2, 3, 4, 2, 3, 1, 4, 2]),
+    "one_order": (_DS, [3] * len(_DS)),
+    "four_orders": (_DS, [(i % 4) + 1 for i in range(len(_DS))]),
 }
 
 
@@ -69,12 +70,14 @@ def test_work_queue_across_launches():
         vals, x = _inputs(ds, 960 + len(plans))
         bp = fsi.BatchPlan(ds, ls, dtype="f32")
         sch = bp.schedule()
-        tiles = sum(1 << max(d - 11, 0) for d in ds)
-        say(f"[case] work queue {name}: {len(ds)} instances, {tiles} tiles, "
-            f"{sch['tiles_per_item']} tile(s) per item, {bp.num_stages()} stages")
+        tpi = sch["tiles_per_item"]
+        tiles = [1 << max(d - 11, 0) for d in ds]
+        items = sum(-(-t // tpi) for t in tiles)
+        say(f"[case] work queue {name}: {len(ds)} instances, {sum(tiles)} tiles, "
+            f"{tpi} tile(s) per item, {items} items, {bp.num_stages()} stages")
         assert sch["fast_instances"] == len(ds)
         # more work items than the grid's workgroups: the queue is used
-        assert tiles // sch["tiles_per_item"] > 512
+        assert items > 512
         plans[name] = (bp, vals, x, ds, ls)
     # interleave the two plans' launch sequences
     runs = {name: [] for name in plans}
