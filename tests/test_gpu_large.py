@@ -1,7 +1,7 @@
 """The operator at the largest sizes one MI355X holds in core (d = 26 to 30;
-the paper's own method stops near d = 25 for memory). FP32 storage, on the
-register-phase kernel (at l = 4 past d = 20 in blocks of 2^6 tiles whose
-partial sums the wide gather combines).
+the paper's own method stops near d = 25 for memory). FP32 storage, and FP64
+at d = 26 and 28, on the register-phase kernel (at l = 4 past d = 20 in blocks
+of 2^6 tiles whose partial sums the wide gather combines).
 
 
 d = 26 and 28: sampled outputs against the C oracle, which evaluates only the
@@ -171,3 +171,25 @@ def test_blocked_register_kernel_in_a_batch():
         ref = oracle.fsi_exact_int(v, d, l, nthreads=16)
         assert normwise(eager[bp.out_offset[i]:bp.out_offset[i + 1]], ref) < 1e-12, (i, d, l)
     bp.close()
+
+
+@pytest.mark.parametrize("d,l", [(26, 4), (28, 3)])
+def test_large_d_fp64_planted_closed_form(d, l):
+    """FP64 storage at large d on the register-phase kernel (d = 26, l = 4 in
+    blocks of 2^6 tiles; d = 28, l = 3 one block) on a planted game with
+    N(0, 1) coefficients: the unanimity closed form of Eq. 3 + Eq. 4 summed
+    over the terms, 1e-12 normwise, and efficiency."""
+    from paper_2601_01903_amd import fsi
+    say(f"[case] large d={d} l={l} FP64 planted, closed form")
+    g = games.planted_game(d, 24, 6, games.rng_for(931, d))
+    v = games.planted_values(g)
+    plan = fsi.Plan(d, l, dtype="f64")
+    assert plan.schedule()["fast_instances"] == 1
+    out = plan.apply(torch.from_numpy(v).to(DEV))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    plan.close()
+    del out
+    want = P.fsi_sparse_mobius(zip(g.masks, g.coefs), d, l)
+    assert normwise(got, want) < 1e-12
+    assert abs(got.sum() - v[-1]) < 1e-12 * max(1.0, np.abs(got).sum())
