@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 # one order (l = 3, d from 9 to 20) and four orders on the same shapes:
-# 8624 tiles, cut by the default schedule into more work items than the 512
+# 8624 tiles, cut by the default schedule into more work items than the
 # workgroups of the grid (asserted below)
 _DS = [20] * 16 + [12, 19, 11, 16, 14, 9, 18, 13]
 CASES = {
@@ -76,8 +76,9 @@ def test_work_queue_across_launches():
         say(f"[case] work queue {name}: {len(ds)} instances, {sum(tiles)} tiles, "
             f"{tpi} tile(s) per item, {items} items, {bp.num_stages()} stages")
         assert sch["fast_instances"] == len(ds)
-        # more work items than the grid's workgroups: the queue is used
-        assert items > 512
+        # more work items than the grid's workgroups (two per CU): the queue
+        # is used
+        assert items > 2 * torch.cuda.get_device_properties(0).multi_processor_count
         plans[name] = (bp, vals, x, ds, ls)
     # interleave the two plans' launch sequences
     runs = {name: [] for name in plans}
